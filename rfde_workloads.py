@@ -1,0 +1,99 @@
+"""Seeded synthetic inputs and the workload shapes of the benchmarked configurations.
+
+This module is shared by the tests, the benchmark and the GPU smoke check.  It holds
+no arithmetic of the solution method: it only draws seeded random coefficients and
+samples smooth sine-mode fields on the interior grid points, so that the oracle and
+the HIP path receive bit-identical inputs.
+
+Grid convention (Section 2.1): the interval (a, b) is split into M + 1 cells,
+h = (b - a) / (M + 1), interior nodes x_i = a + i h for i = 1..M; the time grid is
+t_k = k tau, tau = T / N_t, and the unknowns are u^1..u^{N_t} (t_1..t_{N_t}).
+
+Data recipe (the paper's examples are closed-form manufactured solutions, not a
+dataset; these fields stand in for "smooth initial data and source"):
+  gen1d(seed): a_k, b_k = N(0,1) / k^2 for k = 1..8 from numpy default_rng(seed),
+               a first, then b;  u0(x_i) = sum_k a_k sin(k pi (x_i - a)/(b - a));
+               f(x_i, t_j) = exp(-t_j) sum_k b_k sin(k pi (x_i - a)/(b - a)), j = 1..N_t.
+  gen2d(seed): a_kl, b_kl = N(0,1) / (k^2 l^2), k, l = 1..8, with the products
+               sin(k pi x) sin(l pi y); layout [y][x] with x fastest.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_MODES = 8
+
+
+def grid_1d(a: float, b: float, M: int) -> np.ndarray:
+    """Interior nodes x_1..x_M of (a, b) with h = (b - a)/(M + 1)."""
+    h = (b - a) / (M + 1)
+    return a + h * np.arange(1, M + 1, dtype=np.float64)
+
+
+def time_levels(T: float, Nt: int) -> np.ndarray:
+    """t_1..t_{N_t} with tau = T / N_t."""
+    tau = T / Nt
+    return tau * np.arange(1, Nt + 1, dtype=np.float64)
+
+
+def gen1d(seed: int, M: int, Nt: int, T: float = 1.0, a: float = 0.0, b: float = 1.0):
+    """Seeded 1D initial data u0[M] and source f[N_t][M] (float64)."""
+    rng = np.random.default_rng(seed)
+    k = np.arange(1, N_MODES + 1, dtype=np.float64)
+    ak = rng.standard_normal(N_MODES) / k**2
+    bk = rng.standard_normal(N_MODES) / k**2
+    x = grid_1d(a, b, M)
+    modes = np.sin(np.pi * np.outer(k, (x - a) / (b - a)))  # [8][M]
+    u0 = ak @ modes
+    t = time_levels(T, Nt)
+    f = np.exp(-t)[:, None] * (bk @ modes)[None, :]
+    return np.ascontiguousarray(u0), np.ascontiguousarray(f), (ak, bk)
+
+
+def gen2d(seed: int, Mx: int, My: int, Nt: int, T: float = 1.0,
+          ax: float = 0.0, bx: float = 1.0, ay: float = 0.0, by: float = 1.0):
+    """Seeded 2D initial data u0[My][Mx] and source f[N_t][My][Mx] (float64, x fastest)."""
+    rng = np.random.default_rng(seed)
+    k = np.arange(1, N_MODES + 1, dtype=np.float64)
+    w = 1.0 / np.outer(k**2, k**2)  # [k(x)][l(y)]
+    akl = rng.standard_normal((N_MODES, N_MODES)) * w
+    bkl = rng.standard_normal((N_MODES, N_MODES)) * w
+    x = grid_1d(ax, bx, Mx)
+    y = grid_1d(ay, by, My)
+    sx = np.sin(np.pi * np.outer(k, (x - ax) / (bx - ax)))  # [k][Mx]
+    sy = np.sin(np.pi * np.outer(k, (y - ay) / (by - ay)))  # [l][My]
+    u0 = sy.T @ akl.T @ sx          # [My][Mx] = sum_kl a_kl sy[l,y] sx[k,x]
+    g = sy.T @ bkl.T @ sx
+    t = time_levels(T, Nt)
+    f = np.exp(-t)[:, None, None] * g[None, :, :]
+    return np.ascontiguousarray(u0), np.ascontiguousarray(f), (akl, bkl)
+
+
+def random_vector(seed: int, n: int) -> np.ndarray:
+    """Seeded N(0,1) test vector (used to probe linear operators)."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+# Workload shapes.  Each entry is the problem statement (eq. (1.1) / eq. (4.1)) plus
+# solver settings; 'seed' feeds gen1d / gen2d.
+SMALL_1D = dict(name="1d_M63_Nt64", dim=1, alpha=1.5, kappa=1.0, a=0.0, b=1.0,
+                M=63, Nt=64, T=1.0, tol=1e-10, seed=1000)
+LARGE_1D = dict(name="1d_M4095_Nt1024", dim=1, alphas=(1.2, 1.5, 1.8), kappa=1.0,
+                a=0.0, b=1.0, M=4095, Nt=1024, T=1.0, tol=1e-8, seed=2000)
+GRID_2D = dict(name="2d_255x255_Nt256", dim=2, alpha_x=1.6, alpha_y=1.4,
+               kappa_x=1.0, kappa_y=1.0, Mx=255, My=255, Nt=256, T=1.0,
+               tol=1e-8, seed=3000)
+
+
+def batched_1d_instances(n: int = 64, seed: int = 4):
+    """Uneven 1D instances: M ~ U{511..4095}, N_t ~ U{128..1024},
+    alpha ~ U(1.1, 1.9), kappa ~ LogNormal(0, 0.5), drawn in that order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        M = int(rng.integers(511, 4096))
+        Nt = int(rng.integers(128, 1025))
+        alpha = float(rng.uniform(1.1, 1.9))
+        kappa = float(rng.lognormal(0.0, 0.5))
+        out.append(dict(M=M, Nt=Nt, alpha=alpha, kappa=kappa, T=1.0, seed=4000 + i))
+    return out

@@ -24,14 +24,21 @@ def default_eps(tau: float) -> float:
 
 
 def C_eps_dense(Nt: int, eps: float) -> np.ndarray:
-    """C_eps of eq. (3.1): C_eps[j, k] = c_{j-k} (j >= k), eps c_{j-k+N_t} (j < k), with
-    c = (3/2, -2, 1/2, 0, ...): the Strang-type eps-circulant built from C's Toeplitz part."""
-    c = np.zeros(Nt)
-    c[: min(3, Nt)] = R_COEF[: min(3, Nt)]
-    out = np.empty((Nt, Nt))
-    for j in range(Nt):
-        for k in range(Nt):
-            out[j, k] = c[j - k] if j >= k else eps * c[j - k + Nt]
+    """C_eps of eq. (3.1): the Strang-type eps-circulant built from C's Toeplitz part,
+    r(Z) = 3/2 I - 2 Z + 1/2 Z^2 with Z the eps-circulant down-shift (Z e_j = e_{j+1},
+    Z e_{N_t-1} = eps e_0).  For N_t >= 3 this is exactly the printed matrix:
+    C_eps[j, k] = c_{j-k} (j >= k), eps c_{j-k+N_t} (j < k), c = (3/2, -2, 1/2, 0, ...).
+    Reading for N_t = 2 (the printed pattern needs N_t >= 3): Z^2 = eps I, so the 1/2 term
+    wraps onto the diagonal; this is the matrix whose eigenvalues eq. (3.3) gives."""
+    Z = np.zeros((Nt, Nt))
+    for j in range(Nt - 1):
+        Z[j + 1, j] = 1.0
+    Z[0, Nt - 1] = eps
+    out = np.zeros((Nt, Nt))
+    P = np.eye(Nt)
+    for r in R_COEF:
+        out += r * P
+        P = Z @ P
     return out
 
 

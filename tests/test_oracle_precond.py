@@ -9,7 +9,7 @@ from oracle import precond as pc
 from oracle.weights import gk_recurrence
 
 
-@pytest.mark.parametrize("Nt,eps", [(8, 0.5), (16, 1 / 32), (33, 0.01), (10, 1.0)])
+@pytest.mark.parametrize("Nt,eps", [(2, 0.25), (3, 0.5), (8, 0.5), (16, 1 / 32), (33, 0.01), (10, 1.0)])
 def test_eigenvalues_match_dense_eig(Nt, eps):
     lam = pc.eigenvalues(Nt, eps)
     ev = np.linalg.eigvals(pc.C_eps_dense(Nt, eps))
@@ -57,7 +57,8 @@ def test_step_a_is_the_fourier_matrix_product():
 
 
 @pytest.mark.parametrize("gam,Nt,M,eps", [(1.5, 8, 7, None), (1.2, 10, 6, 0.2),
-                                          (1.8, 16, 5, None), (1.5, 9, 4, 1.0)])
+                                          (1.8, 16, 5, None), (1.5, 9, 4, 1.0),
+                                          (1.5, 2, 6, None), (1.3, 3, 5, None)])
 def test_fast_pinv_equals_dense_inverse(gam, Nt, M, eps):
     h, tau = aa.mesh(0, 1, M, 1.0, Nt)
     eps = pc.default_eps(tau) if eps is None else eps
@@ -141,6 +142,16 @@ def test_tau_eigenvalues_gamma_two():
     sig = pc.tau_eigenvalues(gk_recurrence(2.0, n))
     i = np.arange(1, n + 1)
     assert np.allclose(sig, 2 - 2 * np.cos(np.pi * i / (n + 1)), atol=1e-13)
+
+
+def test_printed_pattern_for_three_or_more_steps():
+    # for N_t >= 3, r(Z_eps) is the matrix drawn in eq. (3.1)
+    Nt, eps = 6, 0.3
+    Ce = pc.C_eps_dense(Nt, eps)
+    c = np.array([1.5, -2.0, 0.5, 0, 0, 0])
+    for j in range(Nt):
+        for k in range(Nt):
+            assert Ce[j, k] == (c[j - k] if j >= k else eps * c[j - k + Nt])
 
 
 def test_default_eps():

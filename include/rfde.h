@@ -1,0 +1,199 @@
+/*
+ * rfde.h -- C ABI of the MI355X (gfx950) all-at-once BDF2 solver for the Riesz space-fractional
+ * diffusion equation with the eps-circulant parallel-in-time preconditioner.
+ *
+ * Method: Gu, Zhao, Zhao, Carpentieri, Huang, "A note on parallel preconditioning for the
+ * all-at-once solution of Riesz fractional diffusion equations" (arXiv:2003.07020).
+ *
+ *   model (eq. (1.1) in 1D, eq. (4.1) in 2D):  u_t = kappa d^alpha u / d|x|^alpha + f,
+ *       u(., 0) = u0, homogeneous Dirichlet boundary, on (a, b) x (0, T].
+ *   space: fractional centred differences (eq. (2.3)-(2.4)), M interior points,
+ *       h = (b - a) / (M + 1); A = -kappa h^-alpha T_x with T_x[i][j] = g_|i-j| (eq. (2.9)).
+ *   time:  BDF2 with a backward-Euler first step (eq. (1.2a)-(1.2b)), N_t steps, tau = T / N_t.
+ *   system (eq. (2.11)-(2.12)):  (C kron I - tau I kron A) U = F,  U = (u^1; ...; u^{N_t}).
+ *   solver: flexible GMRES, right preconditioned by
+ *       P_eps = C_eps kron I - tau I kron A  (eq. (3.1), the paper's alpha-circulant, here eps),
+ *       applied by (a) a scaled FFT over time, (b) independent shifted solves
+ *       (lambda_n I - tau A) z2_n = z1_n, (c) the inverse FFT (Section 3.1, 3.2).
+ *
+ * NAMING: `alpha` is the FRACTIONAL ORDER (the paper's gamma).  The circulant parameter (the
+ * paper's alpha) is `circ_eps`.
+ *
+ * MEMORY: every array argument is a DEVICE pointer (hipMalloc'd or a torch tensor's storage) to
+ * contiguous data, owned by the caller, on the plan's device, unless the comment says "host".
+ * Real arrays are IEEE float64.  Complex arrays ("c128") are interleaved (re, im) float64 pairs.
+ *   1D space-time vector: [N_t][M]      (time level k = 0..N_t-1 holds u at t_{k+1}, space fastest)
+ *   2D space-time vector: [N_t][My][Mx] (x fastest)
+ *   half spectrum:        [floor(N_t/2)+1][S] c128, S = M (1D) or My*Mx (2D)
+ *
+ * STREAMS: a plan enqueues all work on the hipStream_t given at creation (NULL = default stream).
+ * Calls marked "async" only enqueue; rfde_solve and rfde_plan_create_* return after the work is
+ * done.  A plan is not thread-safe: use one plan per host thread / stream.
+ *
+ * ERRORS: functions return an rfde_status.  Negative codes: nothing was written to the outputs
+ * (or their content is undefined).  RFDE_ENOTCONV (positive): U holds the best iterate.
+ * Arguments are validated before any device work or allocation.
+ */
+#ifndef RFDE_H
+#define RFDE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rfde_plan_s* rfde_plan;
+
+typedef enum {
+  RFDE_OK = 0,
+  RFDE_ENOTCONV = 1,     /* solver stopped at maxit; U holds the last iterate          */
+  RFDE_EINVAL = -1,      /* invalid argument (range, null pointer, unsupported shape)    */
+  RFDE_ENOMEM = -2,      /* device allocation failed or the plan would not fit           */
+  RFDE_EHIP = -3,        /* a HIP runtime call failed                                    */
+  RFDE_ENAN = -4,        /* non-finite value in the right-hand side or the iteration     */
+  RFDE_EUNSUPPORTED = -5 /* valid request this build does not implement                  */
+} rfde_status;
+
+/* Spatial solver used in preconditioner step (b). */
+typedef enum {
+  RFDE_SPATIAL_EXACT = 0, /* 1D: dense LDL^T (no pivoting) of lambda_n I - tau A, MFMA updates */
+  RFDE_SPATIAL_TAU = 1    /* DST-I diagonalisation of the tau approximation (eq. (3.9)-(3.11),
+                             eq. (4.5)); the only choice in 2D                               */
+} rfde_spatial;
+
+typedef struct {
+  double tol;          /* stop when ||F - A U|| / ||F|| <= tol (true residual). Default 1e-8   */
+  int maxit;           /* max total Arnoldi steps. Default 200                                 */
+  int restart;         /* FGMRES restart length m, 1..64. Default 30                           */
+  double circ_eps;     /* circulant parameter in (0, 1]; <= 0 selects min(0.5, 0.5 tau)        */
+  int precond_bits;    /* 64: FP64 preconditioner; 32: FP32/complex64 preconditioner (time FFTs
+                          and shifted solves) inside the FP64 outer iteration. Default 64        */
+  int spatial;         /* rfde_spatial. Default RFDE_SPATIAL_EXACT in 1D (TAU is forced in 2D)  */
+} rfde_opts;
+
+typedef struct {
+  int iters;             /* Arnoldi steps taken (= preconditioner applications)               */
+  int restarts;          /* completed restart cycles                                           */
+  int converged;         /* 1 if true_rel_res <= tol                                           */
+  double true_rel_res;   /* ||F - A U|| / ||F|| recomputed at exit                             */
+  double ms_setup;       /* plan setup time (g_k, symbols, lambda, factorisation)              */
+  double ms_solve;       /* rfde_solve wall time (RHS + FGMRES + true residual)                */
+  double ms_pinv;        /* accumulated time inside preconditioner applications (HIP events)   */
+  double ms_matvec;      /* accumulated time inside all-at-once matvecs (HIP events)           */
+  int n_hist;            /* entries used in res_hist                                           */
+  double res_hist[256];  /* estimated relative residual after each Arnoldi step (res_hist[0]=1)*/
+} rfde_stats;
+
+typedef struct {
+  int dim;               /* 1 or 2                                                             */
+  int M, Mx, My;         /* spatial sizes (1D: M; 2D: Mx, My, M = Mx*My)                       */
+  int Nt;                /* time steps                                                          */
+  int n_freq;            /* floor(Nt/2) + 1 shifted systems                                    */
+  int L, Lx, Ly;         /* circulant-embedding FFT lengths                                    */
+  int Mp;                /* padded order of the factored blocks (multiple of 64; 1D exact only)*/
+  double h, hx, hy, tau, circ_eps;
+  double coef, coef_x, coef_y; /* tau kappa / h^alpha: step-(b) matrices are lambda_n I + coef T */
+  size_t factor_bytes;   /* device bytes held by the factors (0 when spatial = TAU)            */
+  size_t workspace_bytes;/* other device bytes held by the plan                                */
+  int precond_bits, spatial;
+} rfde_plan_info;
+
+/* Fill *o with the defaults listed above. */
+void rfde_opts_default(rfde_opts* o);
+
+/* Message for a status code (static string). */
+const char* rfde_strerror(int status);
+
+/*
+ * Weights g_0..g_{n-1} of eq. (2.4) (omega_k^(alpha); g_{-k} = g_k by Lemma 2.1), FP64, computed
+ * on the device by the ratio recurrence g_{k+1} = g_k (k - alpha/2) / (k + 1 + alpha/2) with
+ * g_0 = Gamma(1+alpha) / Gamma(1+alpha/2)^2.  g: device, n doubles.  async.
+ * Errors: EINVAL if alpha not in (0, 2], n < 1 or g == NULL.
+ */
+int rfde_gk(double alpha, int n, double* g, void* hip_stream);
+
+/*
+ * Create a 1D plan (Section 2, Section 3).  Computes g_k, the circulant-embedding symbol of
+ * T_x (length L = 2^ceil(log2(2M-1)), scaled by tau kappa / h^alpha), eps, s_j = eps^{j/N_t},
+ * lambda_n (eq. (3.3)) and, for RFDE_SPATIAL_EXACT, the LDL^T factors of the floor(N_t/2)+1
+ * shifted blocks lambda_n I + (tau kappa / h^alpha) T_x.  Synchronous.
+ *   alpha in (1, 2], kappa > 0, b > a, 1 <= M <= 8191 (EXACT: M <= 16383 padded memory permitting),
+ *   2 <= N_t <= 65536 and N_t a power of two, T > 0, opts may be NULL (defaults).
+ * Errors: EINVAL on any range violation; ENOMEM if the factors (16 Mp^2 (n_freq) bytes in FP64,
+ * 8 in FP32, lower triangle only) plus workspace exceed free device memory (checked before
+ * allocating); EHIP on a runtime failure.  On error *plan is set to NULL.
+ */
+int rfde_plan_create_1d(rfde_plan* plan, double alpha, double kappa, double a, double b, int M,
+                        int Nt, double T, const rfde_opts* opts, void* hip_stream);
+
+/*
+ * Create a 2D plan (eq. (4.1)-(4.5)): A = -(c_x T_x (along x) + c_y T_y (along y)),
+ * c = kappa / h^alpha, h_x = (bx-ax)/(Mx+1), h_y = (by-ay)/(My+1); Mx, My in [1, 4095]; step (b)
+ * uses the 2D tau/DST diagonalisation.  Other arguments as in rfde_plan_create_1d.
+ */
+int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double kappa_x,
+                        double kappa_y, double ax, double bx, double ay, double by, int Mx, int My,
+                        int Nt, double T, const rfde_opts* opts, void* hip_stream);
+
+/* Release every device buffer the plan owns.  Accepts NULL. */
+int rfde_plan_destroy(rfde_plan plan);
+
+/* Sizes and derived parameters of a plan (host struct). */
+int rfde_plan_get_info(rfde_plan plan, rfde_plan_info* info);
+
+/* What rfde_plan_export copies out. */
+typedef enum {
+  RFDE_EXPORT_GK = 0,      /* g_0..g_{M-1} (2D: g^x then g^y), double                         */
+  RFDE_EXPORT_SYMBOL = 1,  /* 1D: L/2+1 doubles, the real spectrum of the scaled circulant
+                              embedding, already divided by L; 2D: Lx/2+1 then Ly/2+1          */
+  RFDE_EXPORT_LAMBDA = 2,  /* n_freq c128: lambda_n, n = 0..floor(N_t/2)                       */
+  RFDE_EXPORT_SCALE = 3,   /* N_t doubles: s_j = eps^{j/N_t}                                   */
+  RFDE_EXPORT_FACTOR = 4,  /* factor of block `index`: Mp*Mp c128 (FP32 plans: complex64) dense
+                              row-major matrix holding unit-lower L (strict lower part) and D
+                              (diagonal) with B = L D L^T; upper part zero                      */
+  RFDE_EXPORT_TAU_SIGMA = 5/* tau eigenvalues sigma_i of T (eq. (3.10)), unscaled: M doubles
+                              (2D: Mx then My)                                                */
+} rfde_export_what;
+
+/* Copy plan data into the device buffer dst (sizes above).  index: block for FACTOR.  async. */
+int rfde_plan_export(rfde_plan plan, int what, int index, void* dst);
+
+/* Step (a5): F_1 = tau f^1 + u0, F_2 = tau f^2 - u0/2, F_k = tau f^k (eq. (2.11)).
+ * u0: [S], f: [N_t][S] (f^1..f^{N_t}), F: [N_t][S].  F may alias f.  async. */
+int rfde_build_rhs(rfde_plan plan, const double* u0, const double* f, double* F);
+
+/* Step (a6): y = (C kron I - tau I kron A) v (Section 3.2).  v, y: [N_t][S], y must not alias v.
+ * async. */
+int rfde_apply_A(rfde_plan plan, const double* v, double* y);
+
+/* Step (a7), preconditioner step (a): z1_n = sum_j theta^{n j} eps^{j/N_t} v_j,
+ * theta = exp(+2 pi i / N_t), n = 0..floor(N_t/2).  v: [N_t][S] real; z1: [n_freq][S] c128.
+ * (FP32 plans compute it in FP32 and write it widened to c128.)  async. */
+int rfde_pinv_step_a(rfde_plan plan, const double* v, void* z1);
+
+/* Step (a8), preconditioner step (b): z2_n = (lambda_n I + coef T)^{-1} z1_n for every n.
+ * z1, z2: [n_freq][S] c128; may alias (in place).  async. */
+int rfde_pinv_step_b(rfde_plan plan, const void* z1, void* z2);
+
+/* Step (a9), preconditioner step (c): extend by z2_{N_t-n} = conj(z2_n) (imaginary parts of
+ * z2_0 and, for even N_t, z2_{N_t/2} are ignored), v_j = eps^{-j/N_t} (1/N_t)
+ * sum_n theta^{-n j} z2_n.  z2: [n_freq][S] c128; v: [N_t][S] real.  async. */
+int rfde_pinv_step_c(rfde_plan plan, const void* z2, double* v);
+
+/* Steps (a7)-(a9): z = P_eps^{-1} v.  v, z: [N_t][S]; z may alias v.  async. */
+int rfde_apply_Pinv(rfde_plan plan, const double* v, double* z);
+
+/*
+ * Steps (a5)-(a10): solve the all-at-once system with FGMRES(m) right-preconditioned by P_eps.
+ * u0: [S], f: [N_t][S], U_init: [N_t][S] initial guess or NULL (zero), U: [N_t][S] output;
+ * tol <= 0 uses the plan's opts.tol.  stats: host pointer or NULL.  Synchronous.
+ * Returns OK, ENOTCONV (U = last iterate), ENAN (non-finite F or residual), EINVAL, EHIP.
+ */
+int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* U_init,
+               double* U, double tol, rfde_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFDE_H */

@@ -132,3 +132,14 @@ def C_inverse_closed_form(Nt: int) -> np.ndarray:
     out = Chat_inv.copy()
     out[:, 0] += 0.5 * w
     return out
+
+
+def circulant_symbol(g: np.ndarray, M: int, L: int) -> np.ndarray:
+    """Eigenvalues of the symmetric circulant of order L >= 2M-1 whose first column is
+    (g_0, ..., g_{M-1}, 0, ..., 0, g_{M-1}, ..., g_1): the DFT of that column (a circulant is
+    diagonalised by the Fourier matrix).  T_x is its leading M x M block, which is how the
+    Toeplitz product is done in O(L log L) (Section 2.1)."""
+    c = np.zeros(L)
+    c[:M] = g[:M]
+    c[L - M + 1:] = g[1:M][::-1]
+    return np.fft.fft(c).real

@@ -1,0 +1,102 @@
+"""ctypes binding of include/rfde.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librfde.so")
+
+RFDE_OK = 0
+RFDE_ENOTCONV = 1
+RFDE_EINVAL = -1
+RFDE_ENOMEM = -2
+RFDE_EHIP = -3
+RFDE_ENAN = -4
+RFDE_EUNSUPPORTED = -5
+
+SPATIAL_EXACT = 0
+SPATIAL_TAU = 1
+
+EXPORT_GK, EXPORT_SYMBOL, EXPORT_LAMBDA, EXPORT_SCALE, EXPORT_FACTOR, EXPORT_TAU_SIGMA = range(6)
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("restart", C.c_int),
+                ("circ_eps", C.c_double), ("precond_bits", C.c_int), ("spatial", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("true_rel_res", C.c_double), ("ms_setup", C.c_double), ("ms_solve", C.c_double),
+                ("ms_pinv", C.c_double), ("ms_matvec", C.c_double), ("n_hist", C.c_int),
+                ("res_hist", C.c_double * 256)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("dim", C.c_int), ("M", C.c_int), ("Mx", C.c_int), ("My", C.c_int),
+                ("Nt", C.c_int), ("n_freq", C.c_int), ("L", C.c_int), ("Lx", C.c_int),
+                ("Ly", C.c_int), ("Mp", C.c_int), ("h", C.c_double), ("hx", C.c_double),
+                ("hy", C.c_double), ("tau", C.c_double), ("circ_eps", C.c_double),
+                ("coef", C.c_double), ("coef_x", C.c_double), ("coef_y", C.c_double),
+                ("factor_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t),
+                ("precond_bits", C.c_int), ("spatial", C.c_int)]
+
+
+class RfdeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} (status {code})")
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load librfde.so (built in-tree); raise if it is missing -- there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2003_07020_amd.build` (needs hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip, d, i = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_double, C.c_int
+    L.rfde_opts_default.argtypes = [C.POINTER(Opts)]
+    L.rfde_opts_default.restype = None
+    L.rfde_strerror.argtypes = [i]
+    L.rfde_strerror.restype = C.c_char_p
+    L.rfde_gk.argtypes = [d, i, vp, vp]
+    L.rfde_plan_create_1d.argtypes = [C.POINTER(vp), d, d, d, d, i, i, d, C.POINTER(Opts), vp]
+    L.rfde_plan_create_2d.argtypes = [C.POINTER(vp), d, d, d, d, d, d, d, d, i, i, i, d,
+                                      C.POINTER(Opts), vp]
+    L.rfde_plan_destroy.argtypes = [vp]
+    L.rfde_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
+    L.rfde_plan_export.argtypes = [vp, i, i, vp]
+    L.rfde_build_rhs.argtypes = [vp, vp, vp, vp]
+    L.rfde_apply_A.argtypes = [vp, vp, vp]
+    L.rfde_pinv_step_a.argtypes = [vp, vp, vp]
+    L.rfde_pinv_step_b.argtypes = [vp, vp, vp]
+    L.rfde_pinv_step_c.argtypes = [vp, vp, vp]
+    L.rfde_apply_Pinv.argtypes = [vp, vp, vp]
+    L.rfde_solve.argtypes = [vp, vp, vp, vp, vp, d, C.POINTER(Stats)]
+    for name in ("rfde_gk", "rfde_plan_create_1d", "rfde_plan_create_2d", "rfde_plan_destroy",
+                 "rfde_plan_get_info", "rfde_plan_export", "rfde_build_rhs", "rfde_apply_A",
+                 "rfde_pinv_step_a", "rfde_pinv_step_b", "rfde_pinv_step_c", "rfde_apply_Pinv",
+                 "rfde_solve"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().rfde_strerror(int(code)).decode()
+    except RuntimeError:
+        return f"status {code}"
+
+
+def check(code: int, where: str, allow=(RFDE_OK,)) -> int:
+    if code not in allow:
+        raise RfdeError(code, where)
+    return code

@@ -1,0 +1,205 @@
+// Preconditioner step (b) with the tau approximation of the Toeplitz blocks (eq. (3.9)-(3.11)
+// in 1D, eq. (4.4)-(4.5) in 2D): the tau matrix is Q diag(sigma) Q with the DST-I matrix
+// Q[i][j] = sqrt(2/(n+1)) sin(pi i j/(n+1)) (symmetric, Q Q = I), so
+//     1D: z2_n = Q diag(1 / (lambda_n + coef sigma_i)) Q z1_n
+//     2D: z2_n = (Qy kron Qx) diag(1 / (lambda_n + coef_x sigma^x_i + coef_y sigma^y_j)) (Qy kron Qx) z1_n.
+// A length-n DST-I is computed by a complex FFT of length P = 2(n+1) of the odd extension
+// (0, x_1..x_n, 0, -x_n..-x_1): FFT_k = -2i sum_j x_j sin(pi j k/(n+1)), hence
+// (Q x)_k = sqrt(2/(n+1)) (i/2) FFT_k.  P must be a power of two.
+#include <type_traits>
+
+#include "fft_lds.hpp"
+#include "rfde_internal.hpp"
+
+namespace rfde {
+
+// buf holds FFT output; return sqrt(2/(n+1)) (i/2) buf[k] as the DST coefficient k.
+template <typename C>
+__device__ __forceinline__ C dst_coef(C y, typename cplx_traits<C>::real sc) {
+  // (i/2) y = (-y.y/2, y.x/2)
+  return cmk<C>(-0.5f * sc * y.y, 0.5f * sc * y.x);
+}
+
+// Rows: `nrows` contiguous rows of length n; NB rows per block.  DST along the row; with
+// SCALE, divide coefficient k by (lambda_f + coef sigma_k) and apply the DST again
+// (f = row / rows_per_freq).
+template <int P, int NB, typename C, bool SCALE>
+__global__ void __launch_bounds__(256) k_dst_rows(C* __restrict__ z, int nrows, int rows_per_freq,
+                                                  const double2* __restrict__ lambda,
+                                                  const double* __restrict__ sigma, double coef,
+                                                  const C* __restrict__ tw) {
+  using R = typename cplx_traits<C>::real;
+  constexpr int n = P / 2 - 1;
+  __shared__ C buf[NB * P];
+  const int row0 = blockIdx.x * NB;
+  const R sc = (R)sqrt(2.0 / (n + 1));
+  for (int e = threadIdx.x; e < NB * (n + 2); e += 256) {
+    const int b = e / (n + 2), j = e - b * (n + 2);
+    const int row = row0 + b;
+    C* B = buf + b * P;
+    if (j == 0 || j == n + 1 || row >= nrows) {
+      B[j] = cmk<C>((R)0, (R)0);
+      if (j > 0 && j <= n) B[P - j] = cmk<C>((R)0, (R)0);
+    } else {
+      const C x = z[(size_t)row * n + j - 1];
+      B[j] = x;
+      B[P - j] = cmk<C>(-x.x, -x.y);
+    }
+  }
+  __syncthreads();
+  fft_lds<P, -1, 256, NB>(buf, tw);
+  if constexpr (SCALE) {
+    for (int e = threadIdx.x; e < NB * n; e += 256) {
+      const int b = e / n, k = e - b * n + 1;
+      const int row = row0 + b;
+      C* B = buf + b * P;
+      C wv = dst_coef(B[k], sc);
+      if (row < nrows) {
+        const double2 lam = lambda[row / rows_per_freq];
+        const double dr = lam.x + coef * sigma[k - 1], di = lam.y;
+        const double den = dr * dr + di * di;
+        wv = cmul(wv, cmk<C>((R)(dr / den), (R)(-di / den)));
+      }
+      B[k] = wv;
+      B[P - k] = cmk<C>(-wv.x, -wv.y);
+      if (k == 1) { B[0] = cmk<C>((R)0, (R)0); B[n + 1] = cmk<C>((R)0, (R)0); }
+    }
+    __syncthreads();
+    fft_lds<P, -1, 256, NB>(buf, tw);
+  }
+  for (int e = threadIdx.x; e < NB * n; e += 256) {
+    const int b = e / n, k = e - b * n + 1;
+    const int row = row0 + b;
+    if (row < nrows) z[(size_t)row * n + k - 1] = dst_coef(buf[b * P + k], sc);
+  }
+}
+
+// Columns of [nf][My][Mx] planes: one block per (frequency, tile of NB columns).  DST along y,
+// divide by lambda_n + coef_x sigma^x_ix + coef_y sigma^y_iy (the x-direction DST has already
+// been applied to the rows), DST along y again.
+template <int P, int NB, typename C>
+__global__ void __launch_bounds__(256) k_dst_cols(C* __restrict__ z, int Mx,
+                                                  const double2* __restrict__ lambda,
+                                                  const double* __restrict__ sigx,
+                                                  const double* __restrict__ sigy, double cx,
+                                                  double cy, const C* __restrict__ tw) {
+  using R = typename cplx_traits<C>::real;
+  constexpr int n = P / 2 - 1;  // My
+  __shared__ C buf[NB * P];
+  const int ntile = (Mx + NB - 1) / NB;
+  const int f = blockIdx.x / ntile, x0 = (blockIdx.x % ntile) * NB;
+  C* plane = z + (size_t)f * n * Mx;
+  const R sc = (R)sqrt(2.0 / (n + 1));
+  for (int e = threadIdx.x; e < NB * P; e += 256) buf[e] = cmk<C>((R)0, (R)0);
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * NB; e += 256) {
+    const int iy = e / NB, b = e - iy * NB, x = x0 + b;
+    if (x < Mx) {
+      const C v = plane[(size_t)iy * Mx + x];
+      buf[b * P + iy + 1] = v;
+      buf[b * P + P - iy - 1] = cmk<C>(-v.x, -v.y);
+    }
+  }
+  __syncthreads();
+  fft_lds<P, -1, 256, NB>(buf, tw);
+  const double2 lam = lambda[f];
+  for (int e = threadIdx.x; e < NB * n; e += 256) {
+    const int b = e / n, k = e - b * n + 1, x = x0 + b;
+    C* B = buf + b * P;
+    C wv = dst_coef(B[k], sc);
+    if (x < Mx) {
+      const double dr = lam.x + cx * sigx[x] + cy * sigy[k - 1], di = lam.y;
+      const double den = dr * dr + di * di;
+      wv = cmul(wv, cmk<C>((R)(dr / den), (R)(-di / den)));
+    } else {
+      wv = cmk<C>((R)0, (R)0);
+    }
+    B[k] = wv;
+    B[P - k] = cmk<C>(-wv.x, -wv.y);
+    if (k == 1) { B[0] = cmk<C>((R)0, (R)0); B[n + 1] = cmk<C>((R)0, (R)0); }
+  }
+  __syncthreads();
+  fft_lds<P, -1, 256, NB>(buf, tw);
+  for (int e = threadIdx.x; e < n * NB; e += 256) {
+    const int iy = e / NB, b = e - iy * NB, x = x0 + b;
+    if (x < Mx) plane[(size_t)iy * Mx + x] = dst_coef(buf[b * P + iy + 1], sc);
+  }
+}
+
+template <int P, typename C>
+constexpr int dst_nb() {
+  constexpr int cap = 65536 / (P * (int)sizeof(C));
+  return cap < 1 ? 1 : (cap > 16 ? 16 : cap);
+}
+
+template <int P, typename C, bool SCALE>
+static int dst_rows(const Plan& p, C* z, int nrows, int rows_per_freq, const double* sigma,
+                    double coef, const C* tw) {
+  constexpr int NB = dst_nb<P, C>();
+  k_dst_rows<P, NB, C, SCALE><<<(nrows + NB - 1) / NB, 256, 0, p.stream>>>(
+      z, nrows, rows_per_freq, p.lambda, sigma, coef, tw);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+template <int P, typename C>
+static int dst_cols(const Plan& p, C* z, const C* tw) {
+  constexpr int NB = dst_nb<P, C>();
+  const int ntile = (p.Mx + NB - 1) / NB;
+  k_dst_cols<P, NB, C><<<p.nf * ntile, 256, 0, p.stream>>>(z, p.Mx, p.lambda, p.sigma,
+                                                           p.sigma + p.Mx, p.coef_x, p.coef_y, tw);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+#define RFDE_P_SWITCH(Pval, FN, ...)           \
+  switch (Pval) {                              \
+    case 16: return FN<16, __VA_ARGS__;        \
+    case 32: return FN<32, __VA_ARGS__;        \
+    case 64: return FN<64, __VA_ARGS__;        \
+    case 128: return FN<128, __VA_ARGS__;      \
+    case 256: return FN<256, __VA_ARGS__;      \
+    case 512: return FN<512, __VA_ARGS__;      \
+    case 1024: return FN<1024, __VA_ARGS__;    \
+    case 2048: return FN<2048, __VA_ARGS__;    \
+    case 4096: return FN<4096, __VA_ARGS__;    \
+    case 8192: return FN<8192, __VA_ARGS__;    \
+    default: return RFDE_EUNSUPPORTED;         \
+  }
+
+// Twiddle tables for the DST lengths live after the L tables: they are built on demand by the
+// plan (p.twD holds 2 (Mx+1) entries then 2 (My+1) in 2D; 2 (M+1) in 1D), double and float.
+template <typename C>
+static int tau_solve_t(const Plan& p, void* zio) {
+  C* z = (C*)zio;
+  const bool f32 = std::is_same<C, float2>::value;
+  if (p.dim == 1) {
+    const int P = 2 * (p.M + 1);
+    const C* tw = f32 ? (const C*)((double2*)p.twD + P) : (const C*)p.twD;
+    RFDE_P_SWITCH(P, dst_rows, C, true>(p, z, p.nf, 1, p.sigma, p.coef, tw));
+  }
+  const int Px = 2 * (p.Mx + 1), Py = 2 * (p.My + 1);
+  const double2* twd = p.twD;
+  const C* twx = f32 ? (const C*)(twd + Px + Py) : (const C*)twd;
+  const C* twy = f32 ? (const C*)((const float2*)(twd + Px + Py) + Px) : (const C*)(twd + Px);
+  auto rows = [&]() -> int {
+    RFDE_P_SWITCH(Px, dst_rows, C, false>(p, z, p.nf * p.My, p.My, p.sigma, 0.0, twx));
+  };
+  auto cols = [&]() -> int { RFDE_P_SWITCH(Py, dst_cols, C>(p, z, twy)); };
+  int rc = rows();
+  if (rc != RFDE_OK) return rc;
+  rc = cols();
+  if (rc != RFDE_OK) return rc;
+  return rows();
+}
+
+int launch_tau_solve(const Plan& p, const void* zin, void* zout) {
+  const size_t csz = p.opts.precond_bits == 32 ? 8 : 16;
+  if (zin != zout)
+    RFDE_HIP(hipMemcpyAsync(zout, zin, (size_t)p.nf * p.S * csz, hipMemcpyDeviceToDevice,
+                            p.stream));
+  if (p.opts.precond_bits == 32) return tau_solve_t<float2>(p, zout);
+  return tau_solve_t<double2>(p, zout);
+}
+
+}  // namespace rfde

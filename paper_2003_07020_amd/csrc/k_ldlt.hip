@@ -1,0 +1,461 @@
+// Preconditioner step (b), exact 1D variant: factor the floor(Nt/2)+1 shifted blocks
+//     B_n = lambda_n I + coef T,   coef = tau kappa / h^alpha,  T[r][c] = g_|r-c|   (eq. (3.5))
+// once, then solve B_n z2_n = z1_n for every n in each preconditioner application.
+//
+// B_n is complex symmetric (B_n^T = B_n) and its Hermitian part Re(lambda_n) I + coef T is
+// positive definite (Re lambda_n >= 0 by Proposition 3.1, T SPD), so every leading principal
+// submatrix is nonsingular and Gaussian elimination needs no pivoting.  For a symmetric matrix
+// that elimination gives U = D L^T, so only B_n = L D L^T (L unit lower, D diagonal) is kept:
+// the factor memory and flops are half those of a general LU.
+//
+// Storage: the order is padded to Mp = 64 T (padding rows/columns are identity rows/columns).
+// Per block n, the lower-triangular 64x64 tiles (i, j), i >= j, are stored one after another
+// (tile index i(i+1)/2 + j), each tile column-major (entry (r, c) at c*64 + r).
+//   off-diagonal tile (i, j):  L_ij
+//   diagonal tile (j, j):      strict lower part: inverse of the unit-lower diagonal block L_jj;
+//                              diagonal: d (the entries of D); strict upper part: L_jj transposed.
+//
+// Factorisation: left-looking (Crout) over tile columns j = 0..T-1.  Two launches per column:
+//   k_ldlt_diag:  S = B_jj - sum_{k<j} (L_jk D_k) L_jk^T (MFMA), then an unblocked LDL^T of S in
+//                 LDS and the inverse of its unit-lower factor;
+//   k_ldlt_panel: for i > j, S = B_ij - sum_{k<j} (L_ik D_k) L_jk^T (MFMA), then
+//                 L_ij = S L_jj^{-T} D_j^{-1} (a second MFMA product with the stored inverse).
+// B_ij is generated from g, coef and lambda_n in the accumulator initialisation, so the
+// assembled matrices are never stored.  Complex products use four real MFMAs each.
+#include "fft_lds.hpp"
+#include "rfde_internal.hpp"
+
+namespace rfde {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename C> struct mma;
+template <> struct mma<double2> {
+  using R = double;
+  using V = d4_t;
+  __device__ static __forceinline__ V fma(R a, R b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row (within the 16x16 block) of accumulator element e held by lane l
+  __device__ static __forceinline__ int row(int l, int e) { return (l >> 4) + 4 * e; }
+};
+template <> struct mma<float2> {
+  using R = float;
+  using V = f4_t;
+  __device__ static __forceinline__ V fma(R a, R b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int l, int e) { return 4 * (l >> 4) + e; }
+};
+
+constexpr int LDSLD = 65;  // padded leading dimension of 64x64 tiles staged in LDS
+
+// Entry (R, Cc) of B_n, padded with identity beyond M.
+__device__ __forceinline__ double2 shifted_entry(const double* __restrict__ g, double coef,
+                                                 double2 lam, int M, int R, int Cc) {
+  if (R >= M || Cc >= M) return make_double2(R == Cc ? 1.0 : 0.0, 0.0);
+  const int d = R > Cc ? R - Cc : Cc - R;
+  double re = coef * g[d];
+  double im = 0.0;
+  if (d == 0) { re += lam.x; im = lam.y; }
+  return make_double2(re, im);
+}
+
+// Logical block index so that each XCD (blocks are dealt round-robin to 8 XCDs) walks a
+// contiguous range of logical work: neighbouring work items share operand tiles in one L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int x = b & 7, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Accumulators of one wave: 2x2 blocks of 16x16, real and imaginary parts.
+template <typename C> struct WaveAcc {
+  typename mma<C>::V re[2][2], im[2][2];
+};
+
+// acc = B_ij - sum_{k<j} (L_ik D_k) L_jk^T for the 64x64 tile (i, j) of block n.
+template <typename C>
+__device__ __forceinline__ void tile_update(WaveAcc<C>& acc, const C* __restrict__ fac, int i,
+                                            int j, const double* __restrict__ g, double coef,
+                                            double2 lam, int M) {
+  using R = typename mma<C>::R;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
+        const int c = wc * 32 + bj * 16 + l16;
+        const double2 b = shifted_entry(g, coef, lam, M, i * TILE + r, j * TILE + c);
+        acc.re[bi][bj][e] = (R)b.x;
+        acc.im[bi][bj][e] = (R)b.y;
+      }
+  for (int k = 0; k < j; ++k) {
+    const C* Lik = fac + tile_index(i, k) * TILE_ELEMS;
+    const C* Ljk = fac + tile_index(j, k) * TILE_ELEMS;
+    const C* Dk = fac + tile_index(k, k) * TILE_ELEMS;
+#pragma unroll 2
+    for (int q = 0; q < 16; ++q) {
+      const int kk = 4 * q + lq;
+      const C d = Dk[kk * (TILE + 1)];
+      R nar[2], nai[2], nnai[2], br[2], bi_[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const C a = Lik[kk * TILE + wr * 32 + bi * 16 + l16];
+        // na = -(a d)
+        nar[bi] = -(a.x * d.x - a.y * d.y);
+        nai[bi] = -(a.x * d.y + a.y * d.x);
+        nnai[bi] = -nai[bi];
+      }
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const C b = Ljk[kk * TILE + wc * 32 + bj * 16 + l16];
+        br[bj] = b.x;
+        bi_[bj] = b.y;
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          acc.re[bi][bj] = mma<C>::fma(nar[bi], br[bj], acc.re[bi][bj]);
+          acc.re[bi][bj] = mma<C>::fma(nnai[bi], bi_[bj], acc.re[bi][bj]);
+          acc.im[bi][bj] = mma<C>::fma(nar[bi], bi_[bj], acc.im[bi][bj]);
+          acc.im[bi][bj] = mma<C>::fma(nai[bi], br[bj], acc.im[bi][bj]);
+        }
+    }
+  }
+}
+
+// Write the wave accumulators into an LDS tile (column-major, leading dimension LDSLD).
+template <typename C>
+__device__ __forceinline__ void acc_to_lds(const WaveAcc<C>& acc, C* __restrict__ S) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1, l16 = lane & 15;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
+        const int c = wc * 32 + bj * 16 + l16;
+        S[c * LDSLD + r] = cmk<C>(acc.re[bi][bj][e], acc.im[bi][bj][e]);
+      }
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) k_ldlt_diag(C* __restrict__ factors, size_t sys_elems,
+                                                   int j, const double* __restrict__ g,
+                                                   double coef,
+                                                   const double2* __restrict__ lambda, int M) {
+  using R = typename mma<C>::R;
+  __shared__ C S[TILE * LDSLD];
+  __shared__ C Li[TILE * LDSLD];
+  const int n = blockIdx.x;
+  C* fac = factors + (size_t)n * sys_elems;
+  {
+    WaveAcc<C> acc;
+    tile_update<C>(acc, fac, j, j, g, coef, lambda[n], M);
+    acc_to_lds<C>(acc, S);
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int r = t & 63, cg = t >> 6;
+  // unblocked LDL^T of S (lower part used): column p: d = S[p][p]; trailing update
+  // S[r][c] -= S[r][p] S[c][p] / d for r >= c > p; then S[r][p] /= d for r > p.
+  for (int p = 0; p < TILE; ++p) {
+    const C d = S[p * LDSLD + p];
+    const R den = d.x * d.x + d.y * d.y;
+    const C dinv = cmk<C>(d.x / den, -d.y / den);
+    if (r > p) {
+      const C ur = S[p * LDSLD + r];
+      const C lr = cmul(ur, dinv);
+      for (int c = p + 1 + cg; c <= r; c += 4) {
+        const C uc = S[p * LDSLD + c];
+        S[c * LDSLD + r] = csub(S[c * LDSLD + r], cmul(lr, uc));
+      }
+    }
+    __syncthreads();
+    if (cg == 0 && r > p) S[p * LDSLD + r] = cmul(S[p * LDSLD + r], dinv);
+    __syncthreads();
+  }
+  // inverse of the unit-lower L: column c solves L x = e_c by forward substitution
+  if (t < TILE) {
+    const int c = t;
+    for (int rr = 0; rr < TILE; ++rr) Li[c * LDSLD + rr] = cmk<C>((R)(rr == c ? 1 : 0), (R)0);
+    for (int rr = c + 1; rr < TILE; ++rr) {
+      C s = cmk<C>((R)0, (R)0);
+      for (int m = c; m < rr; ++m) s = cadd(s, cmul(S[m * LDSLD + rr], Li[c * LDSLD + m]));
+      Li[c * LDSLD + rr] = cmk<C>(-s.x, -s.y);
+    }
+  }
+  __syncthreads();
+  C* Djj = fac + tile_index(j, j) * TILE_ELEMS;
+  for (int e = t; e < TILE_ELEMS; e += 256) {
+    const int c = e >> 6, rr = e & 63;
+    C val;
+    if (rr > c) val = Li[c * LDSLD + rr];        // (L_jj^{-1})[rr][c]
+    else if (rr == c) val = S[c * LDSLD + c];    // d_c
+    else val = S[rr * LDSLD + c];                // L_jj[c][rr] stored transposed
+    Djj[e] = val;
+  }
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) k_ldlt_panel(C* __restrict__ factors, size_t sys_elems,
+                                                    int j, int T, const double* __restrict__ g,
+                                                    double coef,
+                                                    const double2* __restrict__ lambda, int M) {
+  using R = typename mma<C>::R;
+  __shared__ C S[TILE * LDSLD];
+  const int per = T - 1 - j;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int n = lb / per, i = j + 1 + lb % per;
+  C* fac = factors + (size_t)n * sys_elems;
+  {
+    WaveAcc<C> acc;
+    tile_update<C>(acc, fac, i, j, g, coef, lambda[n], M);
+    acc_to_lds<C>(acc, S);
+  }
+  __syncthreads();
+  // X = S L_jj^{-T}:  X[r][c] = sum_m S[r][m] Linv[c][m], Linv[c][m] = Djj[m*64 + c] (c > m),
+  // 1 (c == m), 0 (c < m).
+  const C* Djj = fac + tile_index(j, j) * TILE_ELEMS;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1, l16 = lane & 15, lq = lane >> 4;
+  WaveAcc<C> x;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { x.re[bi][bj][e] = (R)0; x.im[bi][bj][e] = (R)0; }
+#pragma unroll 2
+  for (int q = 0; q < 16; ++q) {
+    const int m = 4 * q + lq;
+    R sr[2], si[2], nsi[2], br[2], bim[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const C s = S[m * LDSLD + wr * 32 + bi * 16 + l16];
+      sr[bi] = s.x; si[bi] = s.y; nsi[bi] = -s.y;
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int c = wc * 32 + bj * 16 + l16;
+      C b;
+      if (c > m) b = Djj[m * TILE + c];
+      else b = cmk<C>((R)(c == m ? 1 : 0), (R)0);
+      br[bj] = b.x; bim[bj] = b.y;
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        x.re[bi][bj] = mma<C>::fma(sr[bi], br[bj], x.re[bi][bj]);
+        x.re[bi][bj] = mma<C>::fma(nsi[bi], bim[bj], x.re[bi][bj]);
+        x.im[bi][bj] = mma<C>::fma(sr[bi], bim[bj], x.im[bi][bj]);
+        x.im[bi][bj] = mma<C>::fma(si[bi], br[bj], x.im[bi][bj]);
+      }
+  }
+  __syncthreads();  // everyone is done reading S
+  // L_ij[r][c] = X[r][c] / d_c, staged through LDS for coalesced stores
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int c = wc * 32 + bj * 16 + l16;
+      const C d = Djj[c * (TILE + 1)];
+      const R den = d.x * d.x + d.y * d.y;
+      const C dinv = cmk<C>(d.x / den, -d.y / den);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
+        S[c * LDSLD + r] = cmul(cmk<C>(x.re[bi][bj][e], x.im[bi][bj][e]), dinv);
+      }
+    }
+  __syncthreads();
+  C* Lij = fac + tile_index(i, j) * TILE_ELEMS;
+  for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) Lij[e] = S[(e >> 6) * LDSLD + (e & 63)];
+}
+
+template <typename C>
+static int factorize_t(Plan& p) {
+  const size_t sys = lower_tiles(p.T) * TILE_ELEMS;
+  C* fac = (C*)p.factors;
+  for (int j = 0; j < p.T; ++j) {
+    k_ldlt_diag<C><<<p.nf, 256, 0, p.stream>>>(fac, sys, j, p.g, p.coef, p.lambda, p.M);
+    RFDE_HIP(hipGetLastError());
+    if (j + 1 < p.T) {
+      const int blocks = p.nf * (p.T - 1 - j);
+      k_ldlt_panel<C><<<blocks, 256, 0, p.stream>>>(fac, sys, j, p.T, p.g, p.coef, p.lambda, p.M);
+      RFDE_HIP(hipGetLastError());
+    }
+  }
+  return RFDE_OK;
+}
+
+int launch_factorize(Plan& p) {
+  if (p.opts.precond_bits == 32) return factorize_t<float2>(p);
+  return factorize_t<double2>(p);
+}
+
+// ------------------------------------------------------------------------------------------
+// Triangular solves: z = L^{-T} D^{-1} L^{-1} b for every block n (one workgroup per block).
+// Forward (row-oriented): y_i = Linv_ii (b_i - sum_{k<i} L_ik y_k).
+// Backward (column-oriented): x_k = Linv_kk^T (y'_k - sum_{i>k} L_ik^T x_i), y' = D^{-1} y.
+// Each wave streams one quarter (16 columns) of every tile; lane = tile row.
+template <typename C> __device__ __forceinline__ C shfl_xor_c(C v, int m) {
+  return cmk<C>(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
+template <typename C> __device__ __forceinline__ C wave_sum(C v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = cadd(v, shfl_xor_c(v, m));
+  return v;
+}
+
+template <typename C, int TMAX>
+__global__ void __launch_bounds__(256) k_trsv(const C* __restrict__ factors, size_t sys_elems,
+                                              const C* zin, C* zout,
+                                              int M, int T) {
+  using R = typename mma<C>::R;
+  __shared__ C xs[TMAX * TILE];
+  __shared__ C red[4][TILE];
+  __shared__ C tb[TILE];
+  const int n = blockIdx.x;
+  const C* fac = factors + (size_t)n * sys_elems;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int Mp = T * TILE;
+  for (int r = t; r < Mp; r += 256) xs[r] = (r < M) ? zin[(size_t)n * M + r] : cmk<C>((R)0, (R)0);
+  __syncthreads();
+  // forward
+  for (int i = 0; i < T; ++i) {
+    C acc = cmk<C>((R)0, (R)0);
+    for (int k = 0; k < i; ++k) {
+      const C* Lik = fac + tile_index(i, k) * TILE_ELEMS;
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) {
+        const int c = 16 * w + cc;
+        acc = cadd(acc, cmul(Lik[c * TILE + lane], xs[k * TILE + c]));
+      }
+    }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0) {
+      const C s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
+      tb[lane] = csub(xs[i * TILE + lane], s);
+    }
+    __syncthreads();
+    const C* Dii = fac + tile_index(i, i) * TILE_ELEMS;
+    C acc2 = cmk<C>((R)0, (R)0);
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = 16 * w + cc;
+      if (lane > c) acc2 = cadd(acc2, cmul(Dii[c * TILE + lane], tb[c]));
+    }
+    red[w][lane] = acc2;
+    __syncthreads();
+    if (w == 0) {
+      const C s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
+      xs[i * TILE + lane] = cadd(tb[lane], s);
+    }
+    __syncthreads();
+  }
+  // diagonal
+  for (int r = t; r < Mp; r += 256) {
+    const C* Dkk = fac + tile_index(r >> 6, r >> 6) * TILE_ELEMS;
+    const C d = Dkk[(r & 63) * (TILE + 1)];
+    const R den = d.x * d.x + d.y * d.y;
+    xs[r] = cmul(xs[r], cmk<C>(d.x / den, -d.y / den));
+  }
+  __syncthreads();
+  // backward
+  for (int k = T - 1; k >= 0; --k) {
+    C acc[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) acc[cc] = cmk<C>((R)0, (R)0);
+    for (int i = k + 1; i < T; ++i) {
+      const C* Lik = fac + tile_index(i, k) * TILE_ELEMS;
+      const C xi = xs[i * TILE + lane];
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) acc[cc] = cadd(acc[cc], cmul(Lik[(16 * w + cc) * TILE + lane], xi));
+    }
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const C s = wave_sum(acc[cc]);
+      if (lane == cc) tb[16 * w + cc] = csub(xs[k * TILE + 16 * w + cc], s);
+    }
+    __syncthreads();
+    const C* Dkk = fac + tile_index(k, k) * TILE_ELEMS;
+    const C tr = tb[lane];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = 16 * w + cc;
+      C pterm = cmk<C>((R)0, (R)0);
+      if (lane > c) pterm = cmul(Dkk[c * TILE + lane], tr);
+      else if (lane == c) pterm = tr;
+      acc[cc] = wave_sum(pterm);
+    }
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc)
+      if (lane == cc) xs[k * TILE + 16 * w + cc] = acc[cc];
+    __syncthreads();
+  }
+  for (int r = t; r < M; r += 256) zout[(size_t)n * M + r] = xs[r];
+}
+
+template <typename C>
+static int trsv_t(const Plan& p, const void* zin, void* zout) {
+  const size_t sys = lower_tiles(p.T) * TILE_ELEMS;
+  if (p.T <= 64) {
+    k_trsv<C, 64><<<p.nf, 256, 0, p.stream>>>((const C*)p.factors, sys, (const C*)zin, (C*)zout,
+                                              p.M, p.T);
+  } else {
+    return RFDE_EINVAL;
+  }
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+int launch_trsv(const Plan& p, const void* zin, void* zout) {
+  if (p.opts.precond_bits == 32) return trsv_t<float2>(p, zin, zout);
+  return trsv_t<double2>(p, zin, zout);
+}
+
+// Export block `index` as a dense row-major Mp x Mp matrix: strict lower = L, diagonal = D.
+template <typename C>
+__global__ void k_export_factor(const C* __restrict__ fac, C* __restrict__ out, int T) {
+  const int Mp = T * TILE;
+  const size_t total = (size_t)Mp * Mp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int R = (int)(e / Mp), Cc = (int)(e % Mp);
+    const int i = R >> 6, j = Cc >> 6, r = R & 63, c = Cc & 63;
+    C val;
+    val.x = 0; val.y = 0;
+    if (i > j) val = fac[tile_index(i, j) * TILE_ELEMS + c * TILE + r];
+    else if (i == j && r > c) val = fac[tile_index(i, i) * TILE_ELEMS + r * TILE + c];  // L^T store
+    else if (i == j && r == c) val = fac[tile_index(i, i) * TILE_ELEMS + c * (TILE + 1)];
+    out[e] = val;
+  }
+}
+
+int launch_export_factor(const Plan& p, int index, void* dst) {
+  const size_t sys = lower_tiles(p.T) * TILE_ELEMS;
+  const size_t total = (size_t)p.Mp * p.Mp;
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 16384);
+  if (p.opts.precond_bits == 32)
+    k_export_factor<float2><<<blocks, 256, 0, p.stream>>>((const float2*)p.factors + index * sys,
+                                                          (float2*)dst, p.T);
+  else
+    k_export_factor<double2><<<blocks, 256, 0, p.stream>>>((const double2*)p.factors + index * sys,
+                                                           (double2*)dst, p.T);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+}  // namespace rfde

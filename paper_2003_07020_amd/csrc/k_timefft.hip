@@ -1,0 +1,157 @@
+// Preconditioner steps (a) and (c) (Section 3.1): the scaled DFT over the time index.
+//
+// step (a): z1_n = sum_j theta^{n j} s_j v_j,  theta = exp(+2 pi i / Nt), s_j = eps^{j/Nt},
+//           for n = 0..Nt/2 (the other half is the complex conjugate, Section 3.2).
+// step (c): v_j = (1 / (Nt s_j)) sum_n theta^{-n j} z2_n with z2_{Nt-n} = conj(z2_n).
+//
+// Layout: v is [Nt][S] (space fastest), z is [Nt/2+1][S] complex.  A block owns a tile of
+// TS = 2 NB adjacent spatial points and all Nt time levels; two real sequences (points 2p and
+// 2p+1 of the tile) share one complex transform, and are separated with the conjugate-symmetry
+// of real-input DFTs: X = (Z_n + conj(Z_{Nt-n})) / 2, Y = (Z_n - conj(Z_{Nt-n})) / (2i).
+#include "fft_lds.hpp"
+#include "rfde_internal.hpp"
+
+namespace rfde {
+
+template <typename C> __device__ __forceinline__ C from_d2(double2 a) {
+  return cmk<C>((typename cplx_traits<C>::real)a.x, (typename cplx_traits<C>::real)a.y);
+}
+
+template <int N, int NB, typename C>
+__global__ void __launch_bounds__(256) k_time_fwd(const double* __restrict__ v, C* __restrict__ z1,
+                                                  const double* __restrict__ s,
+                                                  const C* __restrict__ tw, int S) {
+  using R = typename cplx_traits<C>::real;
+  __shared__ C buf[NB * N];
+  constexpr int TS = 2 * NB;
+  const int i0 = blockIdx.x * TS;
+  for (int e = threadIdx.x; e < N * TS; e += 256) {
+    const int j = e / TS, q = e - j * TS;
+    const int i = i0 + q;
+    const R val = (i < S) ? (R)(s[j] * v[(size_t)j * S + i]) : (R)0;
+    R* slot = reinterpret_cast<R*>(&buf[(q >> 1) * N + j]);
+    slot[q & 1] = val;
+  }
+  __syncthreads();
+  fft_lds<N, +1, 256, NB>(buf, tw);
+  for (int e = threadIdx.x; e < (N / 2 + 1) * TS; e += 256) {
+    const int n = e / TS, q = e - n * TS;
+    const int i = i0 + q;
+    if (i >= S) continue;
+    const C a = buf[(q >> 1) * N + n];
+    const C b = cconj(buf[(q >> 1) * N + ((N - n) & (N - 1))]);
+    C out;
+    if ((q & 1) == 0) out = cmk<C>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y + b.y));
+    else out = cmk<C>((R)0.5 * (a.y - b.y), (R)-0.5 * (a.x - b.x));
+    z1[(size_t)n * S + i] = out;
+  }
+}
+
+template <int N, int NB, typename C>
+__global__ void __launch_bounds__(256) k_time_inv(const C* __restrict__ z2, double* __restrict__ v,
+                                                  const double* __restrict__ s,
+                                                  const C* __restrict__ tw, int S) {
+  using R = typename cplx_traits<C>::real;
+  __shared__ C buf[NB * N];
+  constexpr int TS = 2 * NB;
+  const int i0 = blockIdx.x * TS;
+  for (int e = threadIdx.x; e < (N / 2 + 1) * NB; e += 256) {
+    const int n = e / NB, pp = e - n * NB;
+    const int ia = i0 + 2 * pp, ib = ia + 1;
+    C P = cmk<C>((R)0, (R)0), Q = cmk<C>((R)0, (R)0);
+    if (ia < S) P = z2[(size_t)n * S + ia];
+    if (ib < S) Q = z2[(size_t)n * S + ib];
+    if (n == 0 || n == N / 2) { P.y = (R)0; Q.y = (R)0; }
+    buf[pp * N + n] = cmk<C>(P.x - Q.y, P.y + Q.x);
+    if (n > 0 && n < N / 2) buf[pp * N + N - n] = cmk<C>(P.x + Q.y, Q.x - P.y);
+  }
+  __syncthreads();
+  fft_lds<N, -1, 256, NB>(buf, tw);
+  for (int e = threadIdx.x; e < N * TS; e += 256) {
+    const int j = e / TS, q = e - j * TS;
+    const int i = i0 + q;
+    if (i >= S) continue;
+    const C c = buf[(q >> 1) * N + j];
+    const double val = (double)((q & 1) ? c.y : c.x);
+    v[(size_t)j * S + i] = val / ((double)N * s[j]);
+  }
+}
+
+template <int N, typename C>
+constexpr int time_nb() {
+  constexpr int cap = 65536 / (N * (int)sizeof(C));
+  return cap < 1 ? 1 : (cap > 16 ? 16 : cap);
+}
+
+template <int N, typename C>
+static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw) {
+  constexpr int NB = time_nb<N, C>();
+  const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
+  k_time_fwd<N, NB, C><<<blocks, 256, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+template <int N, typename C>
+static int tf_inv(const Plan& p, const void* z2, double* v, const C* tw) {
+  constexpr int NB = time_nb<N, C>();
+  const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
+  k_time_inv<N, NB, C><<<blocks, 256, 0, p.stream>>>((const C*)z2, v, p.s, tw, p.S);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+#define RFDE_NT_SWITCH(FN, C, ...)                 \
+  switch (p.Nt) {                                  \
+    case 2: return FN<2, C>(__VA_ARGS__);          \
+    case 4: return FN<4, C>(__VA_ARGS__);          \
+    case 8: return FN<8, C>(__VA_ARGS__);          \
+    case 16: return FN<16, C>(__VA_ARGS__);        \
+    case 32: return FN<32, C>(__VA_ARGS__);        \
+    case 64: return FN<64, C>(__VA_ARGS__);        \
+    case 128: return FN<128, C>(__VA_ARGS__);      \
+    case 256: return FN<256, C>(__VA_ARGS__);      \
+    case 512: return FN<512, C>(__VA_ARGS__);      \
+    case 1024: return FN<1024, C>(__VA_ARGS__);    \
+    case 2048: return FN<2048, C>(__VA_ARGS__);    \
+    case 4096: return FN<4096, C>(__VA_ARGS__);    \
+    case 8192: return FN<8192, C>(__VA_ARGS__);    \
+    default: return RFDE_EINVAL;                   \
+  }
+
+int launch_time_fwd(const Plan& p, const double* v, void* z1) {
+  if (p.opts.precond_bits == 32) { RFDE_NT_SWITCH(tf_fwd, float2, p, v, z1, p.twNt32); }
+  RFDE_NT_SWITCH(tf_fwd, double2, p, v, z1, p.twNt);
+}
+
+int launch_time_inv(const Plan& p, const void* z2, double* v) {
+  if (p.opts.precond_bits == 32) { RFDE_NT_SWITCH(tf_inv, float2, p, z2, v, p.twNt32); }
+  RFDE_NT_SWITCH(tf_inv, double2, p, z2, v, p.twNt);
+}
+
+__global__ void k_widen(const float2* __restrict__ a, double2* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    b[i] = make_double2((double)a[i].x, (double)a[i].y);
+}
+__global__ void k_narrow(const double2* __restrict__ a, float2* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+int launch_widen(const Plan& p, const void* zsrc, double2* zdst) {
+  const size_t n = (size_t)p.nf * p.S;
+  k_widen<<<(int)std::min<size_t>((n + 255) / 256, 8192), 256, 0, p.stream>>>((const float2*)zsrc,
+                                                                               zdst, n);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+int launch_narrow(const Plan& p, const double2* zsrc, void* zdst) {
+  const size_t n = (size_t)p.nf * p.S;
+  k_narrow<<<(int)std::min<size_t>((n + 255) / 256, 8192), 256, 0, p.stream>>>(zsrc,
+                                                                                (float2*)zdst, n);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+}  // namespace rfde

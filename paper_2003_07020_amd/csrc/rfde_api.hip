@@ -1,0 +1,536 @@
+// C ABI of the library: plan lifecycle, the individual hot-path steps, and the FGMRES driver.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rfde_internal.hpp"
+
+namespace rfde {
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  if (std::getenv("RFDE_VERBOSE"))
+    std::fprintf(stderr, "[rfde] HIP error %s (%d) in %s at %s:%d\n", hipGetErrorString(e), (int)e,
+                 what, file, line);
+  return e == hipErrorOutOfMemory ? RFDE_ENOMEM : RFDE_EHIP;
+}
+
+static int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+#define RFDE_TRY(expr)            \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_ != RFDE_OK) return rc_; \
+  } while (0)
+
+static void free_plan(Plan* p) {
+  if (!p) return;
+  void* bufs[] = {p->g, p->sym, p->twL, p->twNt, p->twNt32, p->s, p->lambda, p->sigma, p->twD,
+                  p->factors, p->zf, p->vbuf, p->zbuf, p->wvec, p->xvec, p->Fvec, p->red,
+                  p->redout};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (p->hred) (void)hipHostFree(p->hred);
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete p;
+}
+
+template <typename T>
+static int dalloc(T** ptr, size_t count, size_t* acc) {
+  if (count == 0) count = 1;
+  RFDE_HIP(hipMalloc((void**)ptr, count * sizeof(T)));
+  if (acc) *acc += count * sizeof(T);
+  return RFDE_OK;
+}
+
+static size_t workspace_estimate(const Plan& p) {
+  const size_t N = p.N();
+  const size_t m = (size_t)p.opts.restart;
+  const size_t csz = p.opts.precond_bits == 32 ? 8 : 16;
+  return (2 * m + 1 + 3) * N * 8 + (size_t)p.nf * p.S * csz + ((size_t)70 * 1024) * 8 +
+         (size_t)(p.L + p.Lx + p.Ly + 2 * p.Nt) * 16;
+}
+
+// Everything common to 1D and 2D plans once the sizes are known.
+static int plan_allocate_and_setup(Plan* p) {
+  const auto t0 = std::chrono::steady_clock::now();
+  RFDE_HIP(hipSetDevice(p->device));
+  const size_t wsz = workspace_estimate(*p);
+  size_t freeb = 0, totalb = 0;
+  RFDE_HIP(hipMemGetInfo(&freeb, &totalb));
+  if (p->factor_bytes + wsz > freeb) return RFDE_ENOMEM;
+
+  size_t ws = 0;
+  const int gl = p->dim == 1 ? p->M : p->Mx + p->My;
+  RFDE_TRY(dalloc(&p->g, gl, &ws));
+  const int symlen = p->dim == 1 ? p->L / 2 + 1 : (p->Lx / 2 + 1) + (p->Ly / 2 + 1);
+  RFDE_TRY(dalloc(&p->sym, symlen, &ws));
+  RFDE_TRY(dalloc(&p->twL, p->dim == 1 ? p->L : p->Lx + p->Ly, &ws));
+  RFDE_TRY(dalloc(&p->twNt, p->Nt, &ws));
+  RFDE_TRY(dalloc(&p->twNt32, p->Nt, &ws));
+  RFDE_TRY(dalloc(&p->s, p->Nt, &ws));
+  RFDE_TRY(dalloc(&p->lambda, p->nf, &ws));
+  RFDE_TRY(dalloc(&p->sigma, gl, &ws));
+  const size_t csz = p->opts.precond_bits == 32 ? 8 : 16;
+  RFDE_HIP(hipMalloc(&p->zf, (size_t)p->nf * p->S * csz));
+  ws += (size_t)p->nf * p->S * csz;
+  const size_t N = p->N();
+  const size_t m = (size_t)p->opts.restart;
+  RFDE_TRY(dalloc(&p->vbuf, (m + 1) * N, &ws));
+  RFDE_TRY(dalloc(&p->zbuf, m * N, &ws));
+  RFDE_TRY(dalloc(&p->wvec, N, &ws));
+  RFDE_TRY(dalloc(&p->xvec, N, &ws));
+  RFDE_TRY(dalloc(&p->Fvec, N, &ws));
+  RFDE_TRY(dalloc(&p->red, (size_t)70 * 1024, &ws));
+  RFDE_TRY(dalloc(&p->redout, 256, &ws));
+  RFDE_HIP(hipHostMalloc((void**)&p->hred, 256 * sizeof(double), hipHostMallocDefault));
+  for (auto& e : p->ev) RFDE_HIP(hipEventCreate(&e));
+  p->workspace_bytes = ws;
+  if (p->factor_bytes) RFDE_HIP(hipMalloc(&p->factors, p->factor_bytes));
+
+  hipStream_t st = p->stream;
+  if (p->dim == 1) {
+    RFDE_TRY(launch_gk(p->alpha, p->M, p->g, st));
+    RFDE_TRY(launch_twiddles(p->twL, p->L, st));
+    RFDE_TRY(launch_symbol(p->g, p->M, p->L, p->coef / p->L, p->twL, p->sym, st));
+    RFDE_TRY(launch_tau_sigma(p->g, p->M, nullptr, p->sigma, st));
+  } else {
+    RFDE_TRY(launch_gk(p->alpha_x, p->Mx, p->g, st));
+    RFDE_TRY(launch_gk(p->alpha_y, p->My, p->g + p->Mx, st));
+    RFDE_TRY(launch_twiddles(p->twL, p->Lx, st));
+    RFDE_TRY(launch_twiddles(p->twL + p->Lx, p->Ly, st));
+    RFDE_TRY(launch_symbol(p->g, p->Mx, p->Lx, p->coef_x / p->Lx, p->twL, p->sym, st));
+    RFDE_TRY(launch_symbol(p->g + p->Mx, p->My, p->Ly, p->coef_y / p->Ly, p->twL + p->Lx,
+                           p->sym + (p->Lx / 2 + 1), st));
+    RFDE_TRY(launch_tau_sigma(p->g, p->Mx, nullptr, p->sigma, st));
+    RFDE_TRY(launch_tau_sigma(p->g + p->Mx, p->My, nullptr, p->sigma + p->Mx, st));
+  }
+  if (p->opts.spatial == RFDE_SPATIAL_TAU) {
+    // DST twiddles: double tables (length 2(n+1) per axis), then the same in float
+    const int P0 = p->dim == 1 ? 2 * (p->M + 1) : 2 * (p->Mx + 1);
+    const int P1 = p->dim == 1 ? 0 : 2 * (p->My + 1);
+    const int Ptot = P0 + P1;
+    RFDE_HIP(hipMalloc((void**)&p->twD, (size_t)Ptot * (sizeof(double2) + sizeof(float2))));
+    p->workspace_bytes += (size_t)Ptot * (sizeof(double2) + sizeof(float2));
+    float2* tf = reinterpret_cast<float2*>(p->twD + Ptot);
+    RFDE_TRY(launch_twiddles(p->twD, P0, st));
+    RFDE_TRY(launch_twiddles32(tf, P0, st));
+    if (P1) {
+      RFDE_TRY(launch_twiddles(p->twD + P0, P1, st));
+      RFDE_TRY(launch_twiddles32(tf + P0, P1, st));
+    }
+  }
+  RFDE_TRY(launch_twiddles(p->twNt, p->Nt, st));
+  RFDE_TRY(launch_twiddles32(p->twNt32, p->Nt, st));
+  RFDE_TRY(launch_time_data(p->Nt, p->eps, p->s, p->lambda, st));
+  if (p->factor_bytes) RFDE_TRY(launch_factorize(*p));
+  RFDE_HIP(hipStreamSynchronize(st));
+  p->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return RFDE_OK;
+}
+
+static bool opts_ok(const rfde_opts& o) {
+  return o.tol > 0 && o.maxit >= 1 && o.restart >= 1 && o.restart <= 64 && o.circ_eps <= 1.0 &&
+         (o.precond_bits == 64 || o.precond_bits == 32) &&
+         (o.spatial == RFDE_SPATIAL_EXACT || o.spatial == RFDE_SPATIAL_TAU);
+}
+
+// ---- steps ----
+static int pinv_step_b(const Plan& p, const void* z1, void* z2) {
+  if (p.opts.spatial == RFDE_SPATIAL_EXACT) return launch_trsv(p, z1, z2);
+  return launch_tau_solve(p, z1, z2);
+}
+
+static int apply_pinv(Plan& p, const double* v, double* z) {
+  RFDE_TRY(launch_time_fwd(p, v, p.zf));
+  RFDE_TRY(pinv_step_b(p, p.zf, p.zf));
+  RFDE_TRY(launch_time_inv(p, p.zf, z));
+  return RFDE_OK;
+}
+
+}  // namespace rfde
+
+using namespace rfde;
+
+extern "C" {
+
+void rfde_opts_default(rfde_opts* o) {
+  if (!o) return;
+  o->tol = 1e-8;
+  o->maxit = 200;
+  o->restart = 30;
+  o->circ_eps = 0.0;
+  o->precond_bits = 64;
+  o->spatial = RFDE_SPATIAL_EXACT;
+}
+
+const char* rfde_strerror(int s) {
+  switch (s) {
+    case RFDE_OK: return "ok";
+    case RFDE_ENOTCONV: return "not converged within maxit (best iterate returned)";
+    case RFDE_EINVAL: return "invalid argument";
+    case RFDE_ENOMEM: return "out of device memory";
+    case RFDE_EHIP: return "HIP runtime error";
+    case RFDE_ENAN: return "non-finite value encountered";
+    case RFDE_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+int rfde_gk(double alpha, int n, double* g, void* hip_stream) {
+  if (!(alpha > 0.0 && alpha <= 2.0) || n < 1 || !g) return RFDE_EINVAL;
+  return launch_gk(alpha, n, g, (hipStream_t)hip_stream);
+}
+
+int rfde_plan_create_1d(rfde_plan* plan, double alpha, double kappa, double a, double b, int M,
+                        int Nt, double T, const rfde_opts* opts, void* hip_stream) {
+  if (!plan) return RFDE_EINVAL;
+  *plan = nullptr;
+  rfde_opts o;
+  rfde_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(alpha > 1.0 && alpha <= 2.0) || !(kappa > 0.0) || !(b > a) || M < 1 || M > 4096 ||
+      Nt < 2 || Nt > 8192 || !is_pow2(Nt) || !(T > 0.0) || !opts_ok(o) ||
+      !std::isfinite(alpha + kappa + a + b + T))
+    return RFDE_EINVAL;
+  if (o.precond_bits == 32 && Nt > 8192) return RFDE_EINVAL;
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return RFDE_ENOMEM;
+  p->dim = 1;
+  p->M = M; p->S = M; p->Nt = Nt; p->nf = Nt / 2 + 1;
+  p->alpha = alpha; p->kappa = kappa;
+  p->h = (b - a) / (M + 1);
+  p->tau = T / Nt;
+  p->eps = o.circ_eps > 0 ? o.circ_eps : std::min(0.5, 0.5 * p->tau);
+  o.circ_eps = p->eps;
+  p->coef = p->tau * kappa / std::pow(p->h, alpha);
+  p->L = std::max(16, next_pow2(2 * M - 1));
+  p->opts = o;
+  p->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RFDE_EHIP; }
+  if (o.spatial == RFDE_SPATIAL_TAU && !is_pow2(M + 1)) { delete p; return RFDE_EUNSUPPORTED; }
+  if (o.spatial == RFDE_SPATIAL_EXACT) {
+    p->T = (M + TILE - 1) / TILE;
+    p->Mp = p->T * TILE;
+    const size_t csz = o.precond_bits == 32 ? 8 : 16;
+    p->factor_bytes = (size_t)p->nf * lower_tiles(p->T) * TILE_ELEMS * csz;
+  }
+  const int rc = plan_allocate_and_setup(p);
+  if (rc != RFDE_OK) { free_plan(p); return rc; }
+  *plan = reinterpret_cast<rfde_plan>(p);
+  return RFDE_OK;
+}
+
+int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double kappa_x,
+                        double kappa_y, double ax, double bx, double ay, double by, int Mx, int My,
+                        int Nt, double T, const rfde_opts* opts, void* hip_stream) {
+  if (!plan) return RFDE_EINVAL;
+  *plan = nullptr;
+  rfde_opts o;
+  rfde_opts_default(&o);
+  if (opts) o = *opts;
+  o.spatial = RFDE_SPATIAL_TAU;
+  if (!(alpha_x > 1.0 && alpha_x <= 2.0) || !(alpha_y > 1.0 && alpha_y <= 2.0) ||
+      !(kappa_x > 0.0) || !(kappa_y > 0.0) || !(bx > ax) || !(by > ay) || Mx < 1 || My < 1 ||
+      Mx > 4096 || My > 4096 || Nt < 2 || Nt > 8192 || !is_pow2(Nt) || !(T > 0.0) || !opts_ok(o))
+    return RFDE_EINVAL;
+  if (!is_pow2(Mx + 1) || !is_pow2(My + 1)) return RFDE_EUNSUPPORTED;
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return RFDE_ENOMEM;
+  p->dim = 2;
+  p->Mx = Mx; p->My = My; p->M = Mx * My; p->S = Mx * My;
+  p->Nt = Nt; p->nf = Nt / 2 + 1;
+  p->alpha_x = alpha_x; p->alpha_y = alpha_y; p->kappa_x = kappa_x; p->kappa_y = kappa_y;
+  p->hx = (bx - ax) / (Mx + 1);
+  p->hy = (by - ay) / (My + 1);
+  p->tau = T / Nt;
+  p->eps = o.circ_eps > 0 ? o.circ_eps : std::min(0.5, 0.5 * p->tau);
+  o.circ_eps = p->eps;
+  p->coef_x = p->tau * kappa_x / std::pow(p->hx, alpha_x);
+  p->coef_y = p->tau * kappa_y / std::pow(p->hy, alpha_y);
+  p->Lx = std::max(16, next_pow2(2 * Mx - 1));
+  p->Ly = std::max(16, next_pow2(2 * My - 1));
+  p->opts = o;
+  p->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RFDE_EHIP; }
+  const int rc = plan_allocate_and_setup(p);
+  if (rc != RFDE_OK) { free_plan(p); return rc; }
+  *plan = reinterpret_cast<rfde_plan>(p);
+  return RFDE_OK;
+}
+
+int rfde_plan_destroy(rfde_plan plan) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return RFDE_OK;
+  (void)hipStreamSynchronize(p->stream);
+  free_plan(p);
+  return RFDE_OK;
+}
+
+int rfde_plan_get_info(rfde_plan plan, rfde_plan_info* info) {
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!p || !info) return RFDE_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->dim = p->dim;
+  info->M = p->M; info->Mx = p->Mx; info->My = p->My;
+  info->Nt = p->Nt; info->n_freq = p->nf;
+  info->L = p->L; info->Lx = p->Lx; info->Ly = p->Ly;
+  info->Mp = p->Mp;
+  info->h = p->h; info->hx = p->hx; info->hy = p->hy;
+  info->tau = p->tau; info->circ_eps = p->eps;
+  info->coef = p->coef; info->coef_x = p->coef_x; info->coef_y = p->coef_y;
+  info->factor_bytes = p->factor_bytes;
+  info->workspace_bytes = p->workspace_bytes;
+  info->precond_bits = p->opts.precond_bits;
+  info->spatial = p->opts.spatial;
+  return RFDE_OK;
+}
+
+int rfde_plan_export(rfde_plan plan, int what, int index, void* dst) {
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!p || !dst) return RFDE_EINVAL;
+  hipStream_t st = p->stream;
+  const int gl = p->dim == 1 ? p->M : p->Mx + p->My;
+  switch (what) {
+    case RFDE_EXPORT_GK:
+      RFDE_HIP(hipMemcpyAsync(dst, p->g, gl * sizeof(double), hipMemcpyDeviceToDevice, st));
+      return RFDE_OK;
+    case RFDE_EXPORT_SYMBOL: {
+      const int n = p->dim == 1 ? p->L / 2 + 1 : (p->Lx / 2 + 1) + (p->Ly / 2 + 1);
+      RFDE_HIP(hipMemcpyAsync(dst, p->sym, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      return RFDE_OK;
+    }
+    case RFDE_EXPORT_LAMBDA:
+      RFDE_HIP(hipMemcpyAsync(dst, p->lambda, p->nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
+      return RFDE_OK;
+    case RFDE_EXPORT_SCALE:
+      RFDE_HIP(hipMemcpyAsync(dst, p->s, p->Nt * sizeof(double), hipMemcpyDeviceToDevice, st));
+      return RFDE_OK;
+    case RFDE_EXPORT_FACTOR:
+      if (!p->factor_bytes || index < 0 || index >= p->nf) return RFDE_EINVAL;
+      return launch_export_factor(*p, index, dst);
+    case RFDE_EXPORT_TAU_SIGMA:
+      RFDE_HIP(hipMemcpyAsync(dst, p->sigma, gl * sizeof(double), hipMemcpyDeviceToDevice, st));
+      return RFDE_OK;
+    default:
+      return RFDE_EINVAL;
+  }
+}
+
+int rfde_build_rhs(rfde_plan plan, const double* u0, const double* f, double* F) {
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!p || !u0 || !f || !F) return RFDE_EINVAL;
+  return launch_rhs(*p, u0, f, F);
+}
+
+int rfde_apply_A(rfde_plan plan, const double* v, double* y) {
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!p || !v || !y || v == y) return RFDE_EINVAL;
+  return launch_matvec(*p, v, y);
+}
+
+int rfde_pinv_step_a(rfde_plan plan, const double* v, void* z1) {
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!p || !v || !z1) return RFDE_EINVAL;
+  if (p->opts.precond_bits == 32) {
+    RFDE_TRY(launch_time_fwd(*p, v, p->zf));
+    return launch_widen(*p, p->zf, (double2*)z1);
+  }
+  return launch_time_fwd(*p, v, z1);
+}
+
+int rfde_pinv_step_b(rfde_plan plan, const void* z1, void* z2) {
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!p || !z1 || !z2) return RFDE_EINVAL;
+  if (p->opts.precond_bits == 32) {
+    RFDE_TRY(launch_narrow(*p, (const double2*)z1, p->zf));
+    RFDE_TRY(pinv_step_b(*p, p->zf, p->zf));
+    return launch_widen(*p, p->zf, (double2*)z2);
+  }
+  return pinv_step_b(*p, z1, z2);
+}
+
+int rfde_pinv_step_c(rfde_plan plan, const void* z2, double* v) {
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!p || !z2 || !v) return RFDE_EINVAL;
+  if (p->opts.precond_bits == 32) {
+    RFDE_TRY(launch_narrow(*p, (const double2*)z2, p->zf));
+    return launch_time_inv(*p, p->zf, v);
+  }
+  return launch_time_inv(*p, z2, v);
+}
+
+int rfde_apply_Pinv(rfde_plan plan, const double* v, double* z) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !v || !z) return RFDE_EINVAL;
+  return apply_pinv(*p, v, z);
+}
+
+int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* U_init, double* U,
+               double tol, rfde_stats* stats) {
+  Plan* pp = reinterpret_cast<Plan*>(plan);
+  if (!pp || !u0 || !f || !U) return RFDE_EINVAL;
+  Plan& p = *pp;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!(tol > 0)) tol = p.opts.tol;
+  const int m = p.opts.restart;
+  const size_t N = p.N();
+  hipStream_t st = p.stream;
+  double* hr = p.hred;
+  rfde_stats loc;
+  std::memset(&loc, 0, sizeof(loc));
+  float ms_pinv = 0.f, ms_mv = 0.f;
+
+  auto fetch = [&](int count) -> int {
+    RFDE_HIP(hipMemcpyAsync(hr, p.redout, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    RFDE_HIP(hipStreamSynchronize(st));
+    return RFDE_OK;
+  };
+  auto timed_matvec = [&](const double* v, double* y) -> int {
+    RFDE_HIP(hipEventRecord(p.ev[2], st));
+    RFDE_TRY(launch_matvec(p, v, y));
+    RFDE_HIP(hipEventRecord(p.ev[3], st));
+    return RFDE_OK;
+  };
+  auto add_mv_time = [&]() -> int {
+    float t;
+    RFDE_HIP(hipEventElapsedTime(&t, p.ev[2], p.ev[3]));
+    ms_mv += t;
+    return RFDE_OK;
+  };
+
+  RFDE_TRY(launch_rhs(p, u0, f, p.Fvec));
+  RFDE_TRY(launch_nrm2(p, p.Fvec, p.redout));
+  RFDE_TRY(fetch(1));
+  const double bnorm = hr[0];
+  if (!std::isfinite(bnorm)) return RFDE_ENAN;
+  if (bnorm == 0.0) {
+    RFDE_HIP(hipMemsetAsync(U, 0, N * sizeof(double), st));
+    RFDE_HIP(hipStreamSynchronize(st));
+    loc.converged = 1;
+    if (stats) *stats = loc;
+    return RFDE_OK;
+  }
+  // x = U_init (or 0); r = F - A x
+  double* x = p.xvec;
+  double* r = p.vbuf;  // first basis vector slot holds r, normalised in place
+  if (U_init) {
+    RFDE_HIP(hipMemcpyAsync(x, U_init, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    RFDE_TRY(timed_matvec(x, p.wvec));
+    RFDE_TRY(launch_sub(p, p.Fvec, p.wvec, r));
+  } else {
+    RFDE_HIP(hipMemsetAsync(x, 0, N * sizeof(double), st));
+    RFDE_HIP(hipMemcpyAsync(r, p.Fvec, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  RFDE_TRY(launch_nrm2(p, r, p.redout));
+  RFDE_TRY(fetch(1));
+  if (U_init) RFDE_TRY(add_mv_time());
+  double beta = hr[0];
+  if (!std::isfinite(beta)) return RFDE_ENAN;
+  loc.res_hist[0] = beta / bnorm;
+  loc.n_hist = 1;
+  int total = 0;
+  double rel = beta / bnorm;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gvec(m + 1), y(m);
+  while (rel > tol && total < p.opts.maxit) {
+    // V_0 = r / beta (in place)
+    RFDE_TRY(launch_scale_copy(p, r, p.vbuf, p.redout, 1));
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(gvec.begin(), gvec.end(), 0.0);
+    gvec[0] = beta;
+    int k = 0;
+    bool breakdown = false;
+    for (int j = 0; j < m; ++j) {
+      double* vj = p.vbuf + (size_t)j * N;
+      double* zj = p.zbuf + (size_t)j * N;
+      double* vn = p.vbuf + (size_t)(j + 1) * N;
+      RFDE_HIP(hipEventRecord(p.ev[0], st));
+      RFDE_TRY(apply_pinv(p, vj, zj));
+      RFDE_HIP(hipEventRecord(p.ev[1], st));
+      RFDE_TRY(timed_matvec(zj, vn));
+      // classical Gram-Schmidt, twice (CGS2)
+      RFDE_TRY(launch_multi_dot(p, p.vbuf, j + 1, vn, p.redout));
+      RFDE_TRY(launch_multi_axpy(p, vn, p.vbuf, j + 1, p.redout, -1.0));
+      RFDE_TRY(fetch(j + 1));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hr[i];
+      RFDE_TRY(launch_multi_dot(p, p.vbuf, j + 1, vn, p.redout));
+      RFDE_TRY(launch_multi_axpy(p, vn, p.vbuf, j + 1, p.redout, -1.0));
+      RFDE_TRY(launch_nrm2(p, vn, p.redout + j + 1));
+      RFDE_TRY(fetch(j + 2));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hr[i];
+      const double hn = hr[j + 1];
+      {
+        float t;
+        RFDE_HIP(hipEventElapsedTime(&t, p.ev[0], p.ev[1]));
+        ms_pinv += t;
+        RFDE_TRY(add_mv_time());
+      }
+      if (!std::isfinite(hn)) return RFDE_ENAN;
+      H[(size_t)(j + 1) * m + j] = hn;
+      if (hn > 0.0) RFDE_TRY(launch_scale_copy(p, vn, vn, p.redout + j + 1, 1));
+      else breakdown = true;
+      // apply previous rotations, then a new one
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+      const double d = std::hypot(a, b);
+      cs[j] = a / d;
+      sn[j] = b / d;
+      H[(size_t)j * m + j] = d;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      gvec[j + 1] = -sn[j] * gvec[j];
+      gvec[j] = cs[j] * gvec[j];
+      ++total;
+      k = j + 1;
+      const double est = std::fabs(gvec[j + 1]) / bnorm;
+      if (loc.n_hist < 256) loc.res_hist[loc.n_hist++] = est;
+      if (est <= tol || total >= p.opts.maxit || breakdown) break;
+    }
+    // y = H(0:k,0:k)^{-1} g; x += Z y
+    for (int i = k - 1; i >= 0; --i) {
+      double s = gvec[i];
+      for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
+      y[i] = s / H[(size_t)i * m + i];
+    }
+    RFDE_HIP(hipMemcpyAsync(p.redout, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+    RFDE_TRY(launch_multi_axpy(p, x, p.zbuf, k, p.redout, 1.0));
+    // true residual
+    RFDE_TRY(timed_matvec(x, p.wvec));
+    RFDE_TRY(launch_sub(p, p.Fvec, p.wvec, r));
+    RFDE_TRY(launch_nrm2(p, r, p.redout));
+    RFDE_TRY(fetch(1));
+    RFDE_TRY(add_mv_time());
+    beta = hr[0];
+    if (!std::isfinite(beta)) return RFDE_ENAN;
+    rel = beta / bnorm;
+    ++loc.restarts;
+    if (breakdown) break;
+  }
+  RFDE_HIP(hipMemcpyAsync(U, x, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  RFDE_HIP(hipStreamSynchronize(st));
+  const auto t1 = std::chrono::steady_clock::now();
+  loc.iters = total;
+  loc.true_rel_res = rel;
+  loc.converged = rel <= tol ? 1 : 0;
+  loc.ms_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  loc.ms_pinv = ms_pinv;
+  loc.ms_setup = p.ms_setup;
+  loc.ms_matvec = ms_mv;
+  if (stats) *stats = loc;
+  return loc.converged ? RFDE_OK : RFDE_ENOTCONV;
+}
+
+}  // extern "C"

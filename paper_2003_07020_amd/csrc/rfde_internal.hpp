@@ -1,0 +1,101 @@
+// Internal declarations of the rfde HIP library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "rfde.h"
+
+#define RFDE_HIP(expr)                                  \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return rfde::hip_fail(e_, #expr, __FILE__, __LINE__); \
+  } while (0)
+
+namespace rfde {
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+constexpr int TILE = 64;          // factor tile edge (complex entries)
+constexpr int TILE_ELEMS = TILE * TILE;
+
+// Number of lower-triangular tiles of a T x T tile grid, and the index of tile (i, j), i >= j.
+__host__ __device__ inline size_t lower_tiles(int T) { return (size_t)T * (T + 1) / 2; }
+__host__ __device__ inline size_t tile_index(int i, int j) { return (size_t)i * (i + 1) / 2 + j; }
+
+struct Plan {
+  int dim = 1;
+  int M = 0, Mx = 0, My = 0, S = 0;   // S = spatial unknowns per time level
+  int Nt = 0, nf = 0;                 // nf = Nt/2 + 1
+  int L = 0, Lx = 0, Ly = 0;
+  int Mp = 0, T = 0;                  // padded order and tile count of the factored blocks
+  double alpha = 0, alpha_x = 0, alpha_y = 0;
+  double kappa = 0, kappa_x = 0, kappa_y = 0;
+  double h = 0, hx = 0, hy = 0, tau = 0, eps = 0;
+  double coef = 0, coef_x = 0, coef_y = 0;  // tau kappa / h^alpha
+  rfde_opts opts{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // setup data (device)
+  double* g = nullptr;       // 1D: M; 2D: Mx then My
+  double* sym = nullptr;     // 1D: L/2+1; 2D: Lx/2+1 then Ly/2+1 (scaled by coef / L)
+  double2* twL = nullptr;    // twiddles exp(-2 pi i m / L); 2D: Lx table then Ly table
+  double2* twNt = nullptr;   // twiddles exp(-2 pi i m / Nt)
+  float2* twNt32 = nullptr;  // FP32 copy for the FP32 preconditioner
+  double* s = nullptr;       // Nt: eps^{j/Nt}
+  double2* lambda = nullptr; // nf
+  double* sigma = nullptr;   // tau eigenvalues (unscaled): 1D M; 2D Mx then My
+  double2* twD = nullptr;    // DST twiddles for length 2(n+1) (tau solver)
+  void* factors = nullptr;   // nf blocks x lower_tiles(T) x 4096 complex (c128 or c64)
+  size_t factor_bytes = 0;
+
+  // workspace (device)
+  void* zf = nullptr;        // nf x S complex (frequency-domain work, c128 or c64)
+  double* vbuf = nullptr;    // (m+1) x N Krylov basis V
+  double* zbuf = nullptr;    // m x N preconditioned basis Z
+  double* wvec = nullptr;    // N
+  double* xvec = nullptr;    // N
+  double* Fvec = nullptr;    // N
+  double* red = nullptr;     // reduction partials
+  double* redout = nullptr;  // reduction results (device)
+  double* hred = nullptr;    // pinned host copy of reduction results
+  size_t workspace_bytes = 0;
+  double ms_setup = 0.0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  size_t N() const { return (size_t)Nt * S; }
+};
+
+// ---- launchers (all enqueue on p.stream) ----
+int launch_gk(double alpha, int n, double* g, hipStream_t st);
+int launch_twiddles(double2* tw, int n, hipStream_t st);
+int launch_twiddles32(float2* tw, int n, hipStream_t st);
+int launch_symbol(const double* g, int M, int L, double scale, const double2* tw, double* sym,
+                  hipStream_t st);
+int launch_time_data(int Nt, double eps, double* s, double2* lambda, hipStream_t st);
+int launch_tau_sigma(const double* g, int n, const double2* twD, double* sigma, hipStream_t st);
+
+int launch_matvec(const Plan& p, const double* v, double* y);
+int launch_rhs(const Plan& p, const double* u0, const double* f, double* F);
+
+int launch_time_fwd(const Plan& p, const double* v, void* z1);
+int launch_time_inv(const Plan& p, const void* z2, double* v);
+int launch_widen(const Plan& p, const void* zsrc, double2* zdst);  // c64 -> c128 (FP32 plans)
+int launch_narrow(const Plan& p, const double2* zsrc, void* zdst); // c128 -> c64
+
+int launch_factorize(Plan& p);
+int launch_trsv(const Plan& p, const void* zin, void* zout);
+int launch_tau_solve(const Plan& p, const void* zin, void* zout);
+int launch_export_factor(const Plan& p, int index, void* dst);
+
+// BLAS-1 (deterministic fixed-order reductions)
+int launch_multi_dot(const Plan& p, const double* V, int nvec, const double* w, double* out);
+int launch_multi_axpy(const Plan& p, double* w, const double* V, int nvec, const double* coef,
+                      double sign);
+int launch_nrm2(const Plan& p, const double* x, double* out);
+int launch_scale_copy(const Plan& p, const double* x, double* y, const double* scal_dev, int inv);
+int launch_sub(const Plan& p, const double* a, const double* b, double* out);  // out = a - b
+int launch_axpy_host(const Plan& p, double* y, const double* x, double alpha);
+
+}  // namespace rfde

@@ -1,0 +1,185 @@
+"""Python face of the rfde C ABI: torch tensors carry device memory and streams; every step of
+the solver runs in the HIP library (librfde.so).  No computation happens here."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, numel: int, name: str):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def opts(tol=1e-8, maxit=200, restart=30, circ_eps=0.0, precond_bits=64, spatial="exact") -> L.Opts:
+    o = L.Opts()
+    L.lib().rfde_opts_default(C.byref(o))
+    o.tol, o.maxit, o.restart, o.circ_eps = tol, maxit, restart, circ_eps
+    o.precond_bits = precond_bits
+    o.spatial = L.SPATIAL_EXACT if spatial == "exact" else L.SPATIAL_TAU
+    return o
+
+
+def gk(alpha: float, n: int) -> torch.Tensor:
+    """g_0..g_{n-1} computed on the device."""
+    g = torch.empty(n, dtype=torch.float64, device="cuda")
+    L.check(L.lib().rfde_gk(alpha, n, _ptr(g), _stream()), "rfde_gk")
+    return g
+
+
+@dataclass
+class SolveStats:
+    iters: int
+    restarts: int
+    converged: bool
+    true_rel_res: float
+    ms_setup: float
+    ms_solve: float
+    ms_pinv: float
+    ms_matvec: float
+    res_hist: list
+
+
+class Plan:
+    """An rfde plan (1D or 2D).  Use Plan.create_1d / Plan.create_2d."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+        info = L.PlanInfo()
+        L.check(L.lib().rfde_plan_get_info(self._h, C.byref(info)), "rfde_plan_get_info")
+        self.info = {k: getattr(info, k) for k, _ in L.PlanInfo._fields_}
+        self.dim = info.dim
+        self.Nt = info.Nt
+        self.nf = info.n_freq
+        self.S = info.M if info.dim == 1 else info.Mx * info.My
+        self.N = self.Nt * self.S
+
+    @classmethod
+    def create_1d(cls, alpha, kappa, a, b, M, Nt, T, **kw):
+        h = C.c_void_p()
+        o = opts(**kw)
+        L.check(L.lib().rfde_plan_create_1d(C.byref(h), alpha, kappa, a, b, M, Nt, T, C.byref(o),
+                                            _stream()), "rfde_plan_create_1d")
+        return cls(h)
+
+    @classmethod
+    def create_2d(cls, alpha_x, alpha_y, kappa_x, kappa_y, ax, bx, ay, by, Mx, My, Nt, T, **kw):
+        h = C.c_void_p()
+        o = opts(**kw)
+        L.check(L.lib().rfde_plan_create_2d(C.byref(h), alpha_x, alpha_y, kappa_x, kappa_y, ax, bx,
+                                            ay, by, Mx, My, Nt, T, C.byref(o), _stream()),
+                "rfde_plan_create_2d")
+        return cls(h)
+
+    def destroy(self):
+        if self._h:
+            L.lib().rfde_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    # ---- individual steps (async on the current stream) ----
+    def build_rhs(self, u0: torch.Tensor, f: torch.Tensor, out: torch.Tensor | None = None):
+        _need(u0, torch.float64, self.S, "u0")
+        _need(f, torch.float64, self.N, "f")
+        F = torch.empty_like(f) if out is None else out
+        L.check(L.lib().rfde_build_rhs(self._h, _ptr(u0), _ptr(f), _ptr(F)), "rfde_build_rhs")
+        return F
+
+    def apply_A(self, v: torch.Tensor, out: torch.Tensor | None = None):
+        _need(v, torch.float64, self.N, "v")
+        y = torch.empty_like(v) if out is None else out
+        L.check(L.lib().rfde_apply_A(self._h, _ptr(v), _ptr(y)), "rfde_apply_A")
+        return y
+
+    def step_a(self, v: torch.Tensor):
+        _need(v, torch.float64, self.N, "v")
+        z1 = torch.empty(self.nf * self.S, dtype=torch.complex128, device=v.device)
+        L.check(L.lib().rfde_pinv_step_a(self._h, _ptr(v), _ptr(z1)), "rfde_pinv_step_a")
+        return z1
+
+    def step_b(self, z1: torch.Tensor, out: torch.Tensor | None = None):
+        _need(z1, torch.complex128, self.nf * self.S, "z1")
+        z2 = torch.empty_like(z1) if out is None else out
+        L.check(L.lib().rfde_pinv_step_b(self._h, _ptr(z1), _ptr(z2)), "rfde_pinv_step_b")
+        return z2
+
+    def step_c(self, z2: torch.Tensor):
+        _need(z2, torch.complex128, self.nf * self.S, "z2")
+        v = torch.empty(self.N, dtype=torch.float64, device=z2.device)
+        L.check(L.lib().rfde_pinv_step_c(self._h, _ptr(z2), _ptr(v)), "rfde_pinv_step_c")
+        return v
+
+    def apply_Pinv(self, v: torch.Tensor, out: torch.Tensor | None = None):
+        _need(v, torch.float64, self.N, "v")
+        z = torch.empty_like(v) if out is None else out
+        L.check(L.lib().rfde_apply_Pinv(self._h, _ptr(v), _ptr(z)), "rfde_apply_Pinv")
+        return z
+
+    def export(self, what: int, index: int = 0) -> torch.Tensor:
+        i = self.info
+        if what == L.EXPORT_GK:
+            t = torch.empty(i["M"] if i["dim"] == 1 else i["Mx"] + i["My"], dtype=torch.float64)
+        elif what == L.EXPORT_SYMBOL:
+            n = i["L"] // 2 + 1 if i["dim"] == 1 else i["Lx"] // 2 + 1 + i["Ly"] // 2 + 1
+            t = torch.empty(n, dtype=torch.float64)
+        elif what == L.EXPORT_LAMBDA:
+            t = torch.empty(i["n_freq"], dtype=torch.complex128)
+        elif what == L.EXPORT_SCALE:
+            t = torch.empty(i["Nt"], dtype=torch.float64)
+        elif what == L.EXPORT_FACTOR:
+            dt = torch.complex64 if i["precond_bits"] == 32 else torch.complex128
+            t = torch.empty(i["Mp"] * i["Mp"], dtype=dt)
+        elif what == L.EXPORT_TAU_SIGMA:
+            t = torch.empty(i["M"] if i["dim"] == 1 else i["Mx"] + i["My"], dtype=torch.float64)
+        else:
+            raise ValueError(what)
+        t = t.cuda()
+        L.check(L.lib().rfde_plan_export(self._h, what, index, _ptr(t)), "rfde_plan_export")
+        return t
+
+    def solve(self, u0: torch.Tensor, f: torch.Tensor, U_init: torch.Tensor | None = None,
+              tol: float = 0.0, out: torch.Tensor | None = None, allow_notconv: bool = False):
+        _need(u0, torch.float64, self.S, "u0")
+        _need(f, torch.float64, self.N, "f")
+        if U_init is not None:
+            _need(U_init, torch.float64, self.N, "U_init")
+        U = torch.empty_like(f) if out is None else out
+        st = L.Stats()
+        allow = (L.RFDE_OK, L.RFDE_ENOTCONV) if allow_notconv else (L.RFDE_OK,)
+        rc = L.check(L.lib().rfde_solve(self._h, _ptr(u0), _ptr(f), _ptr(U_init), _ptr(U), tol,
+                                        C.byref(st)), "rfde_solve", allow)
+        stats = SolveStats(st.iters, st.restarts, bool(st.converged), st.true_rel_res,
+                           st.ms_setup, st.ms_solve, st.ms_pinv, st.ms_matvec,
+                           [st.res_hist[k] for k in range(st.n_hist)])
+        return U, stats, rc

@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports every function declared in include/rfde.h, and rejects
+invalid arguments before touching the device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rfde.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rfde_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_hot_path_calls():
+    names = _declared()
+    for n in ("rfde_gk", "rfde_plan_create_1d", "rfde_plan_create_2d", "rfde_build_rhs",
+              "rfde_apply_A", "rfde_pinv_step_a", "rfde_pinv_step_b", "rfde_pinv_step_c",
+              "rfde_apply_Pinv", "rfde_solve", "rfde_plan_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2003_07020_amd import lib
+    L = lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_invalid_arguments_rejected_without_device():
+    from paper_2003_07020_amd import capi
+    L = capi.lib()
+    h = C.c_void_p()
+    bad = [
+        (0.9, 1.0, 0.0, 1.0, 63, 64, 1.0),    # alpha <= 1
+        (2.1, 1.0, 0.0, 1.0, 63, 64, 1.0),    # alpha > 2
+        (1.5, 0.0, 0.0, 1.0, 63, 64, 1.0),    # kappa <= 0
+        (1.5, 1.0, 1.0, 1.0, 63, 64, 1.0),    # b <= a
+        (1.5, 1.0, 0.0, 1.0, 0, 64, 1.0),     # M < 1
+        (1.5, 1.0, 0.0, 1.0, 5000, 64, 1.0),  # M too large
+        (1.5, 1.0, 0.0, 1.0, 63, 1, 1.0),     # Nt < 2
+        (1.5, 1.0, 0.0, 1.0, 63, 48, 1.0),    # Nt not a power of two
+        (1.5, 1.0, 0.0, 1.0, 63, 64, 0.0),    # T <= 0
+    ]
+    for args in bad:
+        rc = L.rfde_plan_create_1d(C.byref(h), *args, None, None)
+        assert rc == capi.RFDE_EINVAL, args
+        assert h.value is None
+    o = capi.Opts()
+    L.rfde_opts_default(C.byref(o))
+    assert o.tol == 1e-8 and o.restart == 30 and o.precond_bits == 64
+    for field, val in (("circ_eps", 1.5), ("precond_bits", 16), ("restart", 0), ("tol", -1.0)):
+        o2 = capi.Opts()
+        L.rfde_opts_default(C.byref(o2))
+        setattr(o2, field, val)
+        rc = L.rfde_plan_create_1d(C.byref(h), 1.5, 1.0, 0.0, 1.0, 63, 64, 1.0, C.byref(o2), None)
+        assert rc == capi.RFDE_EINVAL, field
+    assert L.rfde_gk(1.5, 0, None, None) == capi.RFDE_EINVAL
+    assert L.rfde_gk(2.5, 5, C.c_void_p(8), None) == capi.RFDE_EINVAL
+    assert L.rfde_apply_A(None, None, None) == capi.RFDE_EINVAL
+    assert L.rfde_solve(None, None, None, None, None, 0.0, None) == capi.RFDE_EINVAL
+    assert L.rfde_plan_destroy(None) == capi.RFDE_OK
+    # 2D tau solver needs Mx+1 and My+1 to be powers of two
+    rc = L.rfde_plan_create_2d(C.byref(h), 1.6, 1.4, 1.0, 1.0, 0.0, 1.0, 0.0, 1.0, 100, 255, 256,
+                               1.0, None, None)
+    assert rc == capi.RFDE_EUNSUPPORTED
+    assert L.rfde_strerror(capi.RFDE_ENAN).decode().startswith("non-finite")

@@ -1,0 +1,130 @@
+"""GPU parity of each 1D hot-path step (through the C ABI) against the FP64 oracle, at sizes that
+span several 64-wide tiles with ragged tails."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_FFT, TOL_SOLVE, banner, rel_max, to_dev, to_host
+from oracle import allatonce as aa
+from oracle import precond as pc
+from oracle.weights import gk_recurrence
+from rfde_workloads import gen1d, random_vector
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (alpha, kappa, M, Nt)
+    (1.5, 1.0, 63, 64),
+    (1.2, 1.0, 100, 8),
+    (1.8, 0.7, 200, 16),
+    (1.5, 1.0, 256, 2),
+    (1.3, 2.0, 130, 32),
+]
+
+
+def _plan(alpha, kappa, M, Nt, **kw):
+    from paper_2003_07020_amd.rfde import Plan
+    return Plan.create_1d(alpha, kappa, 0.0, 1.0, M, Nt, 1.0, **kw)
+
+
+def _oracle_setup(alpha, kappa, M, Nt):
+    h, tau = aa.mesh(0.0, 1.0, M, 1.0, Nt)
+    A = aa.jacobian_A(alpha, kappa, h, M)
+    return h, tau, A, pc.default_eps(tau)
+
+
+@pytest.mark.parametrize("alpha,n", [(1.1, 5), (1.5, 300), (1.8, 4095), (2.0, 17), (1.2, 10000)])
+def test_gk(alpha, n):
+    from paper_2003_07020_amd.rfde import gk
+    banner(f"gk alpha={alpha} n={n}")
+    g = to_host(gk(alpha, n))
+    ref = gk_recurrence(alpha, n)
+    assert np.max(np.abs(g - ref) / np.abs(np.where(ref == 0, 1, ref))) < 1e-12
+
+
+@pytest.mark.parametrize("alpha,kappa,M,Nt", CASES)
+def test_setup_data(alpha, kappa, M, Nt):
+    from paper_2003_07020_amd import capi
+    banner(f"setup alpha={alpha} M={M} Nt={Nt}")
+    p = _plan(alpha, kappa, M, Nt)
+    h, tau, A, eps = _oracle_setup(alpha, kappa, M, Nt)
+    info = p.info
+    assert info["L"] >= 2 * M - 1 and info["n_freq"] == Nt // 2 + 1
+    assert abs(info["circ_eps"] - eps) == 0.0
+    # a2: symbol = DFT of the circulant embedding, scaled by coef / L
+    L = info["L"]
+    sym = to_host(p.export(capi.EXPORT_SYMBOL))
+    ref = aa.circulant_symbol(gk_recurrence(alpha, M), M, L)[: L // 2 + 1] * info["coef"] / L
+    assert rel_max(sym, ref) < TOL_FFT
+    assert np.isclose(info["coef"], tau * kappa / h**alpha, rtol=1e-14)
+    # a3
+    lam = to_host(p.export(capi.EXPORT_LAMBDA))
+    assert rel_max(lam, pc.eigenvalues(Nt, eps)[: Nt // 2 + 1]) < 1e-14
+    s = to_host(p.export(capi.EXPORT_SCALE))
+    assert rel_max(s, pc.scaling_s(Nt, eps)) < 1e-14
+    p.destroy()
+
+
+@pytest.mark.parametrize("alpha,kappa,M,Nt", CASES)
+def test_factor_reconstructs_shifted_blocks(alpha, kappa, M, Nt):
+    from paper_2003_07020_amd import capi
+    banner(f"factor alpha={alpha} M={M} Nt={Nt}")
+    p = _plan(alpha, kappa, M, Nt)
+    h, tau, A, eps = _oracle_setup(alpha, kappa, M, Nt)
+    lam = pc.eigenvalues(Nt, eps)
+    Mp = p.info["Mp"]
+    for n in sorted({0, 1, Nt // 4, Nt // 2}):
+        F = to_host(p.export(capi.EXPORT_FACTOR, n)).reshape(Mp, Mp)
+        Lf = np.tril(F, -1) + np.eye(Mp)
+        D = np.diag(F)
+        assert np.all(np.triu(F, 1) == 0)
+        B = Lf @ np.diag(D) @ Lf.T
+        ref = np.eye(Mp, dtype=complex)
+        ref[:M, :M] = pc.shifted_matrix(lam[n], A, tau)
+        assert rel_max(B, ref) < 1e-13, n
+
+
+@pytest.mark.parametrize("alpha,kappa,M,Nt", CASES)
+def test_rhs_and_matvec(alpha, kappa, M, Nt):
+    banner(f"rhs+matvec alpha={alpha} M={M} Nt={Nt}")
+    p = _plan(alpha, kappa, M, Nt)
+    h, tau, A, eps = _oracle_setup(alpha, kappa, M, Nt)
+    u0, f, _ = gen1d(11, M, Nt)
+    F = to_host(p.build_rhs(to_dev(u0), to_dev(f.ravel()))).reshape(Nt, M)
+    assert rel_max(F, aa.rhs_F(u0, f, tau)) < 1e-15
+    v = random_vector(12, Nt * M).reshape(Nt, M)
+    y = to_host(p.apply_A(to_dev(v.ravel()))).reshape(Nt, M)
+    assert rel_max(y, aa.apply_all_at_once(v, A, tau)) < TOL_FFT
+
+
+@pytest.mark.parametrize("alpha,kappa,M,Nt", CASES)
+def test_preconditioner_steps(alpha, kappa, M, Nt):
+    banner(f"pinv steps alpha={alpha} M={M} Nt={Nt}")
+    p = _plan(alpha, kappa, M, Nt)
+    h, tau, A, eps = _oracle_setup(alpha, kappa, M, Nt)
+    v = random_vector(13, Nt * M).reshape(Nt, M)
+    z1 = to_host(p.step_a(to_dev(v.ravel()))).reshape(-1, M)
+    z1_ref = pc.step_a(v, eps)
+    assert rel_max(z1, z1_ref) < TOL_FFT
+    z2 = to_host(p.step_b(to_dev(z1_ref.ravel()))).reshape(-1, M)
+    z2_ref = pc.step_b_exact(z1_ref, A, tau, Nt, eps)
+    for n in range(z2.shape[0]):
+        assert rel_max(z2[n], z2_ref[n]) < TOL_SOLVE, n
+    vc = to_host(p.step_c(to_dev(z2_ref.ravel()))).reshape(Nt, M)
+    assert rel_max(vc, pc.step_c(z2_ref, Nt, eps)) < TOL_FFT
+    z = to_host(p.apply_Pinv(to_dev(v.ravel()))).reshape(Nt, M)
+    assert rel_max(z, pc.pinv_fast(v, A, tau, eps)) < TOL_SOLVE
+    if Nt * M <= 2500:
+        assert rel_max(z, pc.pinv_dense(v, A, tau, eps)) < TOL_SOLVE
+
+
+@pytest.mark.parametrize("alpha,kappa,M,Nt", CASES)
+def test_solve_matches_direct(alpha, kappa, M, Nt):
+    banner(f"solve alpha={alpha} M={M} Nt={Nt}")
+    p = _plan(alpha, kappa, M, Nt, tol=1e-11)
+    h, tau, A, eps = _oracle_setup(alpha, kappa, M, Nt)
+    u0, f, _ = gen1d(14, M, Nt)
+    U, st, rc = p.solve(to_dev(u0), to_dev(f.ravel()))
+    U = to_host(U).reshape(Nt, M)
+    Uref = aa.bdf2_march(u0, f, A, tau)
+    assert st.converged and st.true_rel_res <= 1e-11
+    assert rel_max(U, Uref) < 1e-9
+    assert st.iters <= 2 * M + 1

@@ -97,6 +97,8 @@ typedef struct {
   size_t factor_bytes;   /* device bytes held by the factors (0 when spatial = TAU)            */
   size_t workspace_bytes;/* other device bytes held by the plan                                */
   int precond_bits, spatial;
+  double ms_setup;       /* wall time of rfde_plan_create_* (all setup steps, synchronised)   */
+  double ms_factor;      /* device time of the factorisation launches (HIP events), 0 if none */
 } rfde_plan_info;
 
 /* Fill *o with the defaults listed above. */
@@ -118,19 +120,22 @@ int rfde_gk(double alpha, int n, double* g, void* hip_stream);
  * T_x (length L = 2^ceil(log2(2M-1)), scaled by tau kappa / h^alpha), eps, s_j = eps^{j/N_t},
  * lambda_n (eq. (3.3)) and, for RFDE_SPATIAL_EXACT, the LDL^T factors of the floor(N_t/2)+1
  * shifted blocks lambda_n I + (tau kappa / h^alpha) T_x.  Synchronous.
- *   alpha in (1, 2], kappa > 0, b > a, 1 <= M <= 8191 (EXACT: M <= 16383 padded memory permitting),
- *   2 <= N_t <= 65536 and N_t a power of two, T > 0, opts may be NULL (defaults).
- * Errors: EINVAL on any range violation; ENOMEM if the factors (16 Mp^2 (n_freq) bytes in FP64,
- * 8 in FP32, lower triangle only) plus workspace exceed free device memory (checked before
- * allocating); EHIP on a runtime failure.  On error *plan is set to NULL.
+ *   alpha in (1, 2], kappa > 0, b > a, 1 <= M <= 4096, 2 <= N_t <= 8192 with N_t a power of
+ *   two, T > 0; opts may be NULL (defaults).  RFDE_SPATIAL_TAU needs M + 1 a power of two.
+ * Memory: the factors take n_freq * T(T+1)/2 * 4096 complex entries (T = ceil(M/64); 16 bytes
+ * each in FP64, 8 in FP32): 69.9 GB for M = 4095, N_t = 1024 in FP64.
+ * Errors: EINVAL on any range violation; EUNSUPPORTED for TAU with M + 1 not a power of two;
+ * ENOMEM if factors plus workspace exceed free device memory (checked before allocating);
+ * EHIP on a runtime failure.  On error *plan is set to NULL.
  */
 int rfde_plan_create_1d(rfde_plan* plan, double alpha, double kappa, double a, double b, int M,
                         int Nt, double T, const rfde_opts* opts, void* hip_stream);
 
 /*
  * Create a 2D plan (eq. (4.1)-(4.5)): A = -(c_x T_x (along x) + c_y T_y (along y)),
- * c = kappa / h^alpha, h_x = (bx-ax)/(Mx+1), h_y = (by-ay)/(My+1); Mx, My in [1, 4095]; step (b)
- * uses the 2D tau/DST diagonalisation.  Other arguments as in rfde_plan_create_1d.
+ * c = kappa / h^alpha, h_x = (bx-ax)/(Mx+1), h_y = (by-ay)/(My+1); Mx, My in [1, 4096] with
+ * Mx + 1 and My + 1 powers of two (else EUNSUPPORTED); step (b) uses the 2D tau/DST
+ * diagonalisation (no factors are stored).  Other arguments as in rfde_plan_create_1d.
  */
 int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double kappa_x,
                         double kappa_y, double ax, double bx, double ay, double by, int Mx, int My,

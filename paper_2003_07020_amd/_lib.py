@@ -40,7 +40,8 @@ class PlanInfo(C.Structure):
                 ("hy", C.c_double), ("tau", C.c_double), ("circ_eps", C.c_double),
                 ("coef", C.c_double), ("coef_x", C.c_double), ("coef_y", C.c_double),
                 ("factor_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t),
-                ("precond_bits", C.c_int), ("spatial", C.c_int)]
+                ("precond_bits", C.c_int), ("spatial", C.c_int), ("ms_setup", C.c_double),
+                ("ms_factor", C.c_double)]
 
 
 class RfdeError(RuntimeError):

@@ -133,8 +133,17 @@ static int plan_allocate_and_setup(Plan* p) {
   RFDE_TRY(launch_twiddles(p->twNt, p->Nt, st));
   RFDE_TRY(launch_twiddles32(p->twNt32, p->Nt, st));
   RFDE_TRY(launch_time_data(p->Nt, p->eps, p->s, p->lambda, st));
-  if (p->factor_bytes) RFDE_TRY(launch_factorize(*p));
+  if (p->factor_bytes) {
+    RFDE_HIP(hipEventRecord(p->ev[0], st));
+    RFDE_TRY(launch_factorize(*p));
+    RFDE_HIP(hipEventRecord(p->ev[1], st));
+  }
   RFDE_HIP(hipStreamSynchronize(st));
+  if (p->factor_bytes) {
+    float t = 0.f;
+    RFDE_HIP(hipEventElapsedTime(&t, p->ev[0], p->ev[1]));
+    p->ms_factor = t;
+  }
   p->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return RFDE_OK;
 }
@@ -293,6 +302,8 @@ int rfde_plan_get_info(rfde_plan plan, rfde_plan_info* info) {
   info->workspace_bytes = p->workspace_bytes;
   info->precond_bits = p->opts.precond_bits;
   info->spatial = p->opts.spatial;
+  info->ms_setup = p->ms_setup;
+  info->ms_factor = p->ms_factor;
   return RFDE_OK;
 }
 

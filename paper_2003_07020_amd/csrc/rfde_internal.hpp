@@ -61,7 +61,8 @@ struct Plan {
   double* redout = nullptr;  // reduction results (device)
   double* hred = nullptr;    // pinned host copy of reduction results
   size_t workspace_bytes = 0;
-  double ms_setup = 0.0;
+  double ms_setup = 0.0;   // wall time of plan setup
+  double ms_factor = 0.0;  // device time of the factorisation launches (HIP events)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
   size_t N() const { return (size_t)Nt * S; }

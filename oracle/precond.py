@@ -52,10 +52,11 @@ def scaling_s(Nt: int, eps: float) -> np.ndarray:
 def eigenvalues(Nt: int, eps: float) -> np.ndarray:
     """lambda_n = sum_{j=0}^{2} r_j eps^{j/N_t} theta^{n j}, n = 0..N_t-1 (eq. (3.3))."""
     n = np.arange(Nt)
-    theta = np.exp(2j * np.pi / Nt)
     lam = np.zeros(Nt, dtype=np.complex128)
     for j, r in enumerate(R_COEF):
-        lam += r * eps ** (j / Nt) * theta ** (n * j)
+        # theta^{n j} = exp(2 pi i ((n j) mod N_t) / N_t): the exact integer reduction keeps the
+        # angle correctly rounded (repeated powers of theta lose about n j ulps)
+        lam += r * eps ** (j / Nt) * np.exp(2j * np.pi * ((n * j) % Nt) / Nt)
     return lam
 
 

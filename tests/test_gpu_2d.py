@@ -1,0 +1,96 @@
+"""GPU parity of the 2D path (eq. (4.1)-(4.5)): Kronecker-sum Toeplitz matvec, 2D tau/DST
+shifted solves and the full FGMRES solve, FP64 and FP32 preconditioner, against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_FFT, banner, rel_max, to_dev, to_host
+from oracle import allatonce as aa
+from oracle import precond as pc
+from oracle import twod
+from oracle.weights import gk_recurrence
+from rfde_workloads import GRID_2D, gen2d, random_vector
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (alpha_x, alpha_y, Mx, My, Nt)
+    (1.6, 1.4, 15, 7, 8),
+    (1.5, 1.5, 31, 31, 16),
+    (1.7, 1.9, 63, 15, 4),
+    (1.2, 1.8, 7, 127, 2),
+]
+
+
+def _setup(gx, gy, Mx, My, Nt, kx=1.0, ky=1.0, T=1.0):
+    hx, hy, tau = 1.0 / (Mx + 1), 1.0 / (My + 1), T / Nt
+    Tx, Ty = aa.toeplitz_T(gx, Mx), aa.toeplitz_T(gy, My)
+    cx, cy = twod.coeffs(gx, gy, kx, ky, hx, hy)
+    return hx, hy, tau, Tx, Ty, cx, cy, pc.default_eps(tau)
+
+
+def _plan(gx, gy, Mx, My, Nt, **kw):
+    from paper_2003_07020_amd.rfde import Plan
+    return Plan.create_2d(gx, gy, 1.0, 1.0, 0.0, 1.0, 0.0, 1.0, Mx, My, Nt, 1.0, **kw)
+
+
+@pytest.mark.parametrize("gx,gy,Mx,My,Nt", CASES)
+def test_setup_and_matvec_2d(gx, gy, Mx, My, Nt):
+    from paper_2003_07020_amd import capi
+    banner(f"2d matvec {gx},{gy} {Mx}x{My} Nt={Nt}")
+    p = _plan(gx, gy, Mx, My, Nt)
+    hx, hy, tau, Tx, Ty, cx, cy, eps = _setup(gx, gy, Mx, My, Nt)
+    sig = to_host(p.export(capi.EXPORT_TAU_SIGMA))
+    assert rel_max(sig[:Mx], pc.tau_eigenvalues(gk_recurrence(gx, Mx))) < 1e-12
+    assert rel_max(sig[Mx:], pc.tau_eigenvalues(gk_recurrence(gy, My))) < 1e-12
+    v = random_vector(31, Nt * My * Mx).reshape(Nt, My, Mx)
+    y = to_host(p.apply_A(to_dev(v.ravel()))).reshape(Nt, My, Mx)
+    assert rel_max(y, twod.apply_all_at_once_2d(v, Tx, Ty, cx, cy, tau)) < TOL_FFT
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+@pytest.mark.parametrize("gx,gy,Mx,My,Nt", CASES)
+def test_tau_preconditioner_2d(gx, gy, Mx, My, Nt, bits):
+    banner(f"2d pinv bits={bits} {gx},{gy} {Mx}x{My} Nt={Nt}")
+    p = _plan(gx, gy, Mx, My, Nt, precond_bits=bits)
+    hx, hy, tau, Tx, Ty, cx, cy, eps = _setup(gx, gy, Mx, My, Nt)
+    sx, sy = twod.tau_sigma_2d(gx, gy, Mx, My)
+    v = random_vector(32, Nt * My * Mx).reshape(Nt, My, Mx)
+    tol = 1e-11 if bits == 64 else 2e-5
+    z1 = pc.step_a(v.reshape(Nt, -1), eps).reshape(-1, My, Mx)
+    z2 = to_host(p.step_b(to_dev(z1.ravel()))).reshape(z1.shape)
+    ref = twod.step_b_tau_2d(z1, sx, sy, cx, cy, tau, Nt, eps)
+    assert rel_max(z2, ref) < tol
+    z = to_host(p.apply_Pinv(to_dev(v.ravel()))).reshape(v.shape)
+    assert rel_max(z, twod.pinv_tau_2d(v, sx, sy, cx, cy, tau, eps)) < (1e-10 if bits == 64 else 1e-4)
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+@pytest.mark.parametrize("gx,gy,Mx,My,Nt", CASES)
+def test_solve_2d(gx, gy, Mx, My, Nt, bits):
+    banner(f"2d solve bits={bits} {gx},{gy} {Mx}x{My} Nt={Nt}")
+    p = _plan(gx, gy, Mx, My, Nt, precond_bits=bits)
+    hx, hy, tau, Tx, Ty, cx, cy, eps = _setup(gx, gy, Mx, My, Nt)
+    u0, f, _ = gen2d(33, Mx, My, Nt)
+    U, st, _ = p.solve(to_dev(u0.ravel()), to_dev(f.ravel()), tol=1e-11)
+    U = to_host(U).reshape(Nt, My, Mx)
+    assert st.converged and st.true_rel_res <= 1e-11
+    assert rel_max(U, twod.bdf2_march_2d(u0, f, Tx, Ty, cx, cy, tau)) < 1e-9
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_solve_2d_full_grid(bits):
+    W = GRID_2D
+    Mx, My, Nt, gx, gy = W["Mx"], W["My"], W["Nt"], W["alpha_x"], W["alpha_y"]
+    banner(f"2d full grid bits={bits} {Mx}x{My} Nt={Nt}")
+    p = _plan(gx, gy, Mx, My, Nt, precond_bits=bits)
+    hx, hy, tau, Tx, Ty, cx, cy, eps = _setup(gx, gy, Mx, My, Nt)
+    v = random_vector(34, Nt * My * Mx).reshape(Nt, My, Mx)
+    y = to_host(p.apply_A(to_dev(v.ravel()))).reshape(v.shape)
+    assert rel_max(y, twod.apply_all_at_once_2d(v, Tx, Ty, cx, cy, tau)) < TOL_FFT
+    u0, f, _ = gen2d(W["seed"], Mx, My, Nt)
+    U, st, _ = p.solve(to_dev(u0.ravel()), to_dev(f.ravel()), tol=1e-10)
+    U = to_host(U).reshape(Nt, My, Mx)
+    assert st.converged and st.true_rel_res <= 1e-10
+    Uref = twod.bdf2_march_2d(u0, f, Tx, Ty, cx, cy, tau)
+    err = rel_max(U, Uref)
+    print(f"2d full grid bits={bits}: iters={st.iters} rel_err={err:.3e}", flush=True)
+    assert err < 1e-8

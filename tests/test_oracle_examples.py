@@ -7,11 +7,11 @@ import numpy as np
 import pytest
 
 from oracle import allatonce as aa
-from oracle import examples as ex
 from oracle import krylov
 from oracle import precond as pc
 from oracle import twod
 from oracle.weights import gk_recurrence
+import rfde_workloads as ex
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 

@@ -69,9 +69,15 @@ def test_shifted_solves_sampled(big):
     for n in (0, 1, 300, NT // 2):
         B = pc.shifted_matrix(lam[n], A, tau)
         ref = sla.lu_solve(sla.lu_factor(B), z1_ref[n])
-        assert rel_max(z2[n], ref) < 1e-9, n
-        # backward error of the GPU solution itself
-        assert np.linalg.norm(B @ z2[n] - z1_ref[n]) <= 1e-12 * np.linalg.norm(z1_ref[n]) * np.linalg.norm(B, 1)
+        # forward error: cond(B_0) ~ 7e5 at alpha = 1.8 (smallest eigenvalue Re lambda_0 +
+        # coef lambda_min(T) ~ 0.015, largest ~ 1.1e4), so each solver is accurate to about
+        # cond * u * sqrt(M) ~ 5e-9; allow 2e-8 between them
+        assert rel_max(z2[n], ref) < 2e-8, n
+        # normwise backward error of the GPU solution itself (the decisive check); the
+        # Wilkinson-type bound for an order-M elimination and residual is ~ M u = 4.5e-13
+        bwd = np.linalg.norm(B @ z2[n] - z1_ref[n]) / (
+            np.linalg.norm(B, 1) * np.linalg.norm(z2[n]) + np.linalg.norm(z1_ref[n]))
+        assert bwd < 1e-13, (n, bwd)
 
 
 def test_preconditioner_identity(big):
@@ -84,7 +90,9 @@ def test_preconditioner_identity(big):
         Pz[k] = 1.5 * z[k] - 2.0 * (z[k - 1] if k >= 1 else eps * z[NT - 1]) \
             + 0.5 * (z[k - 2] if k >= 2 else eps * z[NT - 2 + k])
     Pz -= tau * (z @ A.T)
-    assert rel_max(Pz, v) < 1e-9
+    # a backward-stable apply leaves ||P z - v|| <~ c u ||P|| ||z||, with ||P|| ~ 1.1e4 and
+    # ||z|| <~ ||v|| / 0.015 here: ~7e-11 c, so allow 1e-8
+    assert rel_max(Pz, v) < 1e-8
 
 
 def test_solve_full(big):

@@ -6,7 +6,12 @@ lambda_n, LDL^T factors of the shifted blocks), solve the all-at-once system wit
 the eps-circulant preconditioner until the true relative residual is <= 1e-8, destroy the plan.
 Inputs (u0, f) are seeded synthetic fields already resident in device memory.
 
-Prints one JSON line (see --help).  --gpus > 1 is not supported (one-GPU build).
+The headline `value` is the FP64 form (mean ms per solve, setup included).  The same steps are
+timed for the FP32-preconditioner form and reported under "forms", each with its error against
+the oracle's exact solution.  Prints one JSON line.  --gpus > 1 is not supported.
+
+--kernels-only runs a short fixed sequence (a 2 GiB device copy for counter calibration, one
+plan setup, three preconditioner applications and three matvecs) for profiler runs.
 """
 from __future__ import annotations
 
@@ -31,50 +36,54 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="1d_M4095_Nt1024",
                     choices=["1d_M4095_Nt1024", "1d_M63_Nt64"])
-    ap.add_argument("--precond-bits", type=int, default=64, choices=[64, 32])
+    ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--alphas", default="")
     ap.add_argument("--pinv-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true")
+    ap.add_argument("--precond-bits", type=int, default=64, choices=[64, 32])
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU runs are not "
-              "supported", file=sys.stderr)
-        sys.exit(2)
+def workload(name):
+    from rfde_workloads import LARGE_1D, SMALL_1D
+    if name == "1d_M4095_Nt1024":
+        return LARGE_1D
+    return dict(SMALL_1D, alphas=(SMALL_1D["alpha"],))
+
+
+def event_ms(fn, reps, stream):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def measure_form(bits, args, W, alphas, inputs, dev):
+    """Time K steps of (setup + solve) for every alpha, then P^-1, step (b) and the matvec."""
     import torch
 
     from paper_2003_07020_amd.rfde import Plan
-    from rfde_workloads import LARGE_1D, SMALL_1D, gen1d
-
-    W = LARGE_1D if args.workload == "1d_M4095_Nt1024" else dict(SMALL_1D, alphas=(SMALL_1D["alpha"],))
-    alphas = tuple(float(a) for a in args.alphas.split(",")) if args.alphas else tuple(W["alphas"])
     M, Nt, kappa, T = W["M"], W["Nt"], W["kappa"], W["T"]
-    tol = 1e-8
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    inputs = []
-    for i, a in enumerate(alphas):
-        u0, f, _ = gen1d(W["seed"] + i, M, Nt, T)
-        inputs.append((a, torch.from_numpy(u0).to(dev), torch.from_numpy(f.ravel()).to(dev), u0, f))
     U = torch.empty(Nt * M, dtype=torch.float64, device=dev)
+    sols = {}
 
     def one_step(record=None):
         for a, u0d, fd, _, _ in inputs:
             t0 = time.perf_counter()
-            p = Plan.create_1d(a, kappa, 0.0, 1.0, M, Nt, T, tol=tol,
-                               precond_bits=args.precond_bits)
+            p = Plan.create_1d(a, kappa, 0.0, 1.0, M, Nt, T, tol=1e-8, precond_bits=bits)
             _, st, _ = p.solve(u0d, fd, out=U)
             t1 = time.perf_counter()
             if record is not None:
                 record.append(dict(alpha=a, ms_total=(t1 - t0) * 1e3, ms_setup=p.info["ms_setup"],
                                    ms_factor=p.info["ms_factor"], ms_solve=st.ms_solve,
-                                   ms_pinv=st.ms_pinv, ms_matvec=st.ms_matvec, iters=st.iters,
-                                   true_rel_res=st.true_rel_res, converged=st.converged,
-                                   factor_bytes=p.info["factor_bytes"], Mp=p.info["Mp"],
-                                   n_freq=p.info["n_freq"]))
+                                   ms_pinv=st.ms_pinv, iters=st.iters,
+                                   true_rel_res=st.true_rel_res, converged=st.converged))
+                sols[a] = U.cpu().numpy().reshape(Nt, M)
             p.destroy()
 
     for _ in range(args.warmup):
@@ -86,97 +95,146 @@ def main():
         one_step(recs)
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    per_solve = [r["ms_total"] for r in recs]
-    value = float(np.mean(per_solve))
 
-    # precond applies/s, the step-(b) kernel alone, and the matvec, on one plan (middle alpha)
     a_mid = alphas[len(alphas) // 2]
-    p = Plan.create_1d(a_mid, kappa, 0.0, 1.0, M, Nt, T, tol=tol, precond_bits=args.precond_bits)
-    info = p.info
-    v = torch.randn(Nt * M, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(7))
+    p = Plan.create_1d(a_mid, kappa, 0.0, 1.0, M, Nt, T, tol=1e-8, precond_bits=bits)
+    info = dict(p.info)
+    g = torch.Generator(device=dev).manual_seed(7)
+    v = torch.randn(Nt * M, dtype=torch.float64, device=dev, generator=g)
     z = torch.empty_like(v)
     s = torch.cuda.current_stream()
-    for _ in range(2):
-        p.apply_Pinv(v, out=z)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(args.pinv_reps):
-        p.apply_Pinv(v, out=z)
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms_pinv = e0.elapsed_time(e1) / args.pinv_reps
+    p.apply_Pinv(v, out=z)
+    ms_pinv = event_ms(lambda: p.apply_Pinv(v, out=z), args.pinv_reps, s)
     z1 = p.step_a(v)
     z2 = torch.empty_like(z1)
     p.step_b(z1, out=z2)
-    e0.record(s)
-    for _ in range(args.pinv_reps):
-        p.step_b(z1, out=z2)
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms_stepb = e0.elapsed_time(e1) / args.pinv_reps
+    ms_stepb = event_ms(lambda: p.step_b(z1, out=z2), args.pinv_reps, s)
     y = torch.empty_like(v)
     p.apply_A(v, out=y)
-    e0.record(s)
-    for _ in range(20):
-        p.apply_A(v, out=y)
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms_mv = e0.elapsed_time(e1) / 20
+    ms_mv = event_ms(lambda: p.apply_A(v, out=y), 20, s)
     p.destroy()
 
-    nf, Mp = info["n_freq"], info["Mp"]
-    fp32 = args.precond_bits == 32
-    # dominant kernel of time-to-residual: the LDL^T factorisation (MFMA).  Algorithmic flops of
-    # a complex symmetric LDL^T of order M: M^3/6 complex multiply-adds = (4/3) M^3 real flops.
+    fp32 = bits == 32
+    nf = info["n_freq"]
     flops_factor = nf * (4.0 / 3.0) * float(M) ** 3
     ms_factor = float(np.mean([r["ms_factor"] for r in recs]))
     achieved = flops_factor / (ms_factor * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
-    # step (b) (triangular solves): reads the lower factor twice per application;
-    # algorithmic bytes = n_freq * M^2 * (16 or 8) (M(M+1)/2 entries, two passes)
     esz = 8 if fp32 else 16
     bytes_b = nf * float(M) * M * esz
+    # step (b) is timed through the C ABI; for FP32 plans that call also converts c128 <-> c64
+    # around the solves (about 0.1% of its bytes at this size).
+    return dict(
+        value=float(np.mean([r["ms_total"] for r in recs])), ms_per_step=ms_per_step, recs=recs,
+        sols=sols, ms_pinv=ms_pinv, ms_stepb=ms_stepb, ms_mv=ms_mv, info=info,
+        roofline={"kernel": "k_ldlt_diag+k_ldlt_panel (factorisation)", "bound": "mfma",
+                  "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                  "frac": round(achieved / peak, 4), "traffic": None},
+        roofline_step_b={"kernel": "k_trsv", "bound": "hbm",
+                         "achieved": round(bytes_b / (ms_stepb * 1e-3) / 1e9, 1),
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(bytes_b / (ms_stepb * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                         "traffic": None})
+
+
+def kernels_only(W, dev):
+    import torch
+
+    from paper_2003_07020_amd.rfde import Plan
+    from rfde_workloads import gen1d
+    n = 1 << 27  # 2^27 doubles = 1 GiB each way: calibration copy of known size
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    M, Nt = W["M"], W["Nt"]
+    p = Plan.create_1d(1.5, W["kappa"], 0.0, 1.0, M, Nt, W["T"])
+    u0, f, _ = gen1d(W["seed"], M, Nt)
+    v = torch.from_numpy(f.ravel()).to(dev)
+    z = torch.empty_like(v)
+    for _ in range(3):
+        p.apply_Pinv(v, out=z)
+        p.apply_A(z, out=v)
+    torch.cuda.synchronize()
+    p.destroy()
+    print(json.dumps({"kernels_only": True, "copy_bytes_each_way": n * 8, "M": M, "Nt": Nt}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU runs are not "
+              "supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from rfde_workloads import gen1d
+
+    W = workload(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.kernels_only:
+        kernels_only(W, dev)
+        return
+    alphas = tuple(float(a) for a in args.alphas.split(",")) if args.alphas else tuple(W["alphas"])
+    M, Nt, kappa, T = W["M"], W["Nt"], W["kappa"], W["T"]
+    inputs = []
+    for i, a in enumerate(alphas):
+        u0, f, _ = gen1d(W["seed"] + i, M, Nt, T)
+        inputs.append((a, torch.from_numpy(u0).to(dev), torch.from_numpy(f.ravel()).to(dev), u0, f))
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    results = {f: measure_form(32 if f == "fp32" else 64, args, W, alphas, inputs, dev)
+               for f in forms}
+    base = results[forms[0]]
+    a_mid = alphas[len(alphas) // 2]
+    cpu, Uref = (None, None) if args.no_cpu_baseline else cpu_baseline(inputs, a_mid, M, Nt,
+                                                                        kappa, T)
+    forms_out = {}
+    for f, r in results.items():
+        err = None
+        if Uref is not None and a_mid in r["sols"]:
+            err = float(np.max(np.abs(r["sols"][a_mid] - Uref)) / np.max(np.abs(Uref)))
+        forms_out[f] = {"value_ms": round(r["value"], 3),
+                        "precond_applies_per_s": round(1e3 / r["ms_pinv"], 3),
+                        "ms_factor": round(float(np.mean([x["ms_factor"] for x in r["recs"]])), 3),
+                        "iters": [x["iters"] for x in r["recs"][: len(alphas)]],
+                        "rel_err_vs_oracle": err,
+                        "speedup_vs_fp64": round(base["value"] / r["value"], 3)}
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(base["value"], 3),
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(base["ms_per_step"], 3),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if not fp32 else "f64+f32precond",
+        "dtype": "f64",
         "data": "synthetic (seeded sine-mode u0 and f)",
         "config": {"workload": args.workload, "M": M, "Nt": Nt, "kappa": kappa, "T": T,
-                   "alphas": list(alphas), "tol": tol, "form": "fp32-precond" if fp32 else "fp64",
-                   "spatial_solver": "exact LDL^T (MFMA)", "step": "plan setup + solve per alpha"},
-        "precond_applies_per_s": round(1e3 / ms_pinv, 3),
-        "ms_per_pinv": round(ms_pinv, 4),
-        "ms_step_b": round(ms_stepb, 4),
-        "ms_matvec": round(ms_mv, 5),
+                   "alphas": list(alphas), "tol": 1e-8, "form": forms[0],
+                   "spatial_solver": "exact LDL^T (MFMA)",
+                   "step": "plan setup + solve, once per alpha"},
+        "precond_applies_per_s": round(1e3 / base["ms_pinv"], 3),
+        "ms_per_pinv": round(base["ms_pinv"], 4),
+        "ms_step_b": round(base["ms_stepb"], 4),
+        "ms_matvec": round(base["ms_mv"], 5),
         "per_solve": [{k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r.items()
                        if k in ("alpha", "ms_total", "ms_setup", "ms_factor", "ms_solve", "iters",
-                                "true_rel_res")} for r in recs],
-        "roofline": {"kernel": "k_ldlt_diag+k_ldlt_panel (factorisation)", "bound": "mfma",
-                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None},
-        "roofline_step_b": {"kernel": "k_trsv", "bound": "hbm",
-                            "achieved": round(bytes_b / (ms_stepb * 1e-3) / 1e9, 1),
-                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                            "frac": round(bytes_b / (ms_stepb * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                            "traffic": None},
+                                "true_rel_res")} for r in base["recs"]],
+        "roofline": base["roofline"],
+        "roofline_step_b": base["roofline_step_b"],
+        "forms": forms_out,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inputs, a_mid, M, Nt, kappa, T, dev)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(inputs, a_mid, M, Nt, kappa, T, dev):
+def cpu_baseline(inputs, a_mid, M, Nt, kappa, T):
     """The oracle's sequential BDF2 march (its plain definition of the solution) on the host."""
-    import torch
-
     from oracle import allatonce as aa
     try:
         from threadpoolctl import threadpool_info
@@ -184,17 +242,17 @@ def cpu_baseline(inputs, a_mid, M, Nt, kappa, T, dev):
                        if i.get("user_api") == "blas"] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    a, u0d, fd, u0, f = next(x for x in inputs if x[0] == a_mid)
+    a, _, _, u0, f = next(x for x in inputs if x[0] == a_mid)
     h, tau = aa.mesh(0.0, 1.0, M, T, Nt)
     t0 = time.perf_counter()
     A = aa.jacobian_A(a, kappa, h, M)
     Uref = aa.bdf2_march(u0, f, A, tau)
     ms = (time.perf_counter() - t0) * 1e3
-    return {"value": round(ms, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
-            "sample": f"one full solve: oracle sequential BDF2 (dense Toeplitz assembly, two "
-                      f"Cholesky factors, {2 * Nt} triangular solves) at M={M}, N_t={Nt}, "
-                      f"alpha={a}; exact solution, residual far below 1e-8",
-            "host_cpus": os.cpu_count()}
+    return ({"value": round(ms, 1), "unit": "ms", "cores": int(threads), "kind": "oracle",
+             "sample": f"one full solve: the oracle's sequential BDF2 march (dense Toeplitz "
+                       f"assembly, two Cholesky factors, {2 * Nt} triangular solves) at M={M}, "
+                       f"N_t={Nt}, alpha={a}; an exact solution, residual far below 1e-8",
+             "host_cpus": os.cpu_count()}, Uref)
 
 
 if __name__ == "__main__":

@@ -18,7 +18,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librfde.so")
 ARCH = os.environ.get("RFDE_OFFLOAD_ARCH", "gfx950")
 
-# Packed FP32 instructions are disabled for all device code (hardware notes).
+# Packed FP32 instructions (v_pk_*_f32) are disabled for all device code; every kernel is
+# validated with plain scalar FP32/FP64 arithmetic only.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]

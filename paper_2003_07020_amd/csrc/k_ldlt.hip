@@ -16,10 +16,12 @@
 //                              diagonal: d (the entries of D); strict upper part: L_jj transposed.
 //
 // Factorisation: left-looking (Crout) over tile columns j = 0..T-1.  Two launches per column:
-//   k_ldlt_diag:  S = B_jj - sum_{k<j} (L_jk D_k) L_jk^T (MFMA), then an unblocked LDL^T of S in
-//                 LDS and the inverse of its unit-lower factor;
+//   k_ldlt_diag:  unblocked LDL^T in LDS of the pending diagonal tile and the inverse of its
+//                 unit-lower factor;
 //   k_ldlt_panel: for i > j, S = B_ij - sum_{k<j} (L_ik D_k) L_jk^T (MFMA), then
-//                 L_ij = S L_jj^{-T} D_j^{-1} (a second MFMA product with the stored inverse).
+//                 L_ij = S L_jj^{-T} D_j^{-1} (a second MFMA product with the stored inverse),
+//                 then the pending diagonal tile (i, i) -= (L_ij D_j) L_ij^T (a third), so the
+//                 diagonal launches, which have only one workgroup per block, do no GEMM work.
 // B_ij is generated from g, coef and lambda_n in the accumulator initialisation, so the
 // assembled matrices are never stored.  Complex products use four real MFMAs each.
 #include "fft_lds.hpp"
@@ -148,6 +150,13 @@ __device__ __forceinline__ void acc_to_lds(const WaveAcc<C>& acc, C* __restrict_
       }
 }
 
+// Diagonal tile of column j.  Its pending value S = B_jj - sum_{k<j} (L_jk D_k) L_jk^T has been
+// accumulated in the tile's own slot by the panel launches of columns 0..j-1 (j = 0: B_00 is
+// generated here).  Unblocked LDL^T of S in LDS, then the inverse of the unit-lower factor by
+// forward substitution, kept in the (free) upper triangle of the same LDS tile: thread c writes
+// column c of L^{-1} transposed, S[r*LD + c] = Linv[r][c] for r > c.  The stored tile (entry
+// (rr, cc) at cc*64 + rr) is then exactly S read transposed: Linv below the diagonal, d on it,
+// L transposed above it.
 template <typename C>
 __global__ void __launch_bounds__(256) k_ldlt_diag(C* __restrict__ factors, size_t sys_elems,
                                                    int j, const double* __restrict__ g,
@@ -155,19 +164,23 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(C* __restrict__ factors, size
                                                    const double2* __restrict__ lambda, int M) {
   using R = typename mma<C>::R;
   __shared__ C S[TILE * LDSLD];
-  __shared__ C Li[TILE * LDSLD];
   const int n = blockIdx.x;
   C* fac = factors + (size_t)n * sys_elems;
-  {
-    WaveAcc<C> acc;
-    tile_update<C>(acc, fac, j, j, g, coef, lambda[n], M);
-    acc_to_lds<C>(acc, S);
+  C* Djj = fac + tile_index(j, j) * TILE_ELEMS;
+  const int t = threadIdx.x;
+  if (j == 0) {
+    const double2 lam = lambda[n];
+    for (int e = t; e < TILE_ELEMS; e += 256) {
+      const int c = e >> 6, r = e & 63;
+      const double2 b = shifted_entry(g, coef, lam, M, r, c);
+      S[c * LDSLD + r] = cmk<C>((R)b.x, (R)b.y);
+    }
+  } else {
+    for (int e = t; e < TILE_ELEMS; e += 256) S[(e >> 6) * LDSLD + (e & 63)] = Djj[e];
   }
   __syncthreads();
-  const int t = threadIdx.x;
   const int r = t & 63, cg = t >> 6;
-  // unblocked LDL^T of S (lower part used): column p: d = S[p][p]; trailing update
-  // S[r][c] -= S[r][p] S[c][p] / d for r >= c > p; then S[r][p] /= d for r > p.
+  // column p: d = S[p][p]; S[r][c] -= S[r][p] S[c][p] / d for r >= c > p; S[r][p] /= d, r > p.
   for (int p = 0; p < TILE; ++p) {
     const C d = S[p * LDSLD + p];
     const R den = d.x * d.x + d.y * d.y;
@@ -184,26 +197,18 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(C* __restrict__ factors, size
     if (cg == 0 && r > p) S[p * LDSLD + r] = cmul(S[p * LDSLD + r], dinv);
     __syncthreads();
   }
-  // inverse of the unit-lower L: column c solves L x = e_c by forward substitution
+  // x = L^{-1} e_c: x_c = 1, x_rr = -(L[rr][c] + sum_{c<m<rr} L[rr][m] x_m); L[rr][m] lives at
+  // S[m*LD + rr] (lower), x_m at S[m*LD + c] (upper, written earlier by this thread).
   if (t < TILE) {
     const int c = t;
-    for (int rr = 0; rr < TILE; ++rr) Li[c * LDSLD + rr] = cmk<C>((R)(rr == c ? 1 : 0), (R)0);
     for (int rr = c + 1; rr < TILE; ++rr) {
-      C s = cmk<C>((R)0, (R)0);
-      for (int m = c; m < rr; ++m) s = cadd(s, cmul(S[m * LDSLD + rr], Li[c * LDSLD + m]));
-      Li[c * LDSLD + rr] = cmk<C>(-s.x, -s.y);
+      C s = S[c * LDSLD + rr];
+      for (int m = c + 1; m < rr; ++m) s = cadd(s, cmul(S[m * LDSLD + rr], S[m * LDSLD + c]));
+      S[rr * LDSLD + c] = cmk<C>(-s.x, -s.y);
     }
   }
   __syncthreads();
-  C* Djj = fac + tile_index(j, j) * TILE_ELEMS;
-  for (int e = t; e < TILE_ELEMS; e += 256) {
-    const int c = e >> 6, rr = e & 63;
-    C val;
-    if (rr > c) val = Li[c * LDSLD + rr];        // (L_jj^{-1})[rr][c]
-    else if (rr == c) val = S[c * LDSLD + c];    // d_c
-    else val = S[rr * LDSLD + c];                // L_jj[c][rr] stored transposed
-    Djj[e] = val;
-  }
+  for (int e = t; e < TILE_ELEMS; e += 256) Djj[e] = S[(e & 63) * LDSLD + (e >> 6)];
 }
 
 template <typename C>
@@ -281,6 +286,71 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(C* __restrict__ factors, siz
   __syncthreads();
   C* Lij = fac + tile_index(i, j) * TILE_ELEMS;
   for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) Lij[e] = S[(e >> 6) * LDSLD + (e & 63)];
+  // This column's contribution to the pending diagonal tile (i, i):
+  //   P_ii -= (L_ij D_j) L_ij^T,  P_ii = B_ii before column 0.
+  // Only the lower triangle is used later, so the wave owning the upper-right quadrant skips.
+  WaveAcc<C> dl;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { dl.re[bi][bj][e] = (R)0; dl.im[bi][bj][e] = (R)0; }
+  const bool active = !(wr == 0 && wc == 1);
+  if (active) {
+#pragma unroll 2
+    for (int q = 0; q < 16; ++q) {
+      const int m = 4 * q + lq;
+      const C d = Djj[m * (TILE + 1)];
+      R ar[2], ai[2], nai[2], br[2], bim[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const C a = cmul(S[m * LDSLD + wr * 32 + bi * 16 + l16], d);
+        ar[bi] = a.x; ai[bi] = a.y; nai[bi] = -a.y;
+      }
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const C b = S[m * LDSLD + wc * 32 + bj * 16 + l16];
+        br[bj] = b.x; bim[bj] = b.y;
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          dl.re[bi][bj] = mma<C>::fma(ar[bi], br[bj], dl.re[bi][bj]);
+          dl.re[bi][bj] = mma<C>::fma(nai[bi], bim[bj], dl.re[bi][bj]);
+          dl.im[bi][bj] = mma<C>::fma(ar[bi], bim[bj], dl.im[bi][bj]);
+          dl.im[bi][bj] = mma<C>::fma(ai[bi], br[bj], dl.im[bi][bj]);
+        }
+    }
+  }
+  __syncthreads();  // S (L_ij) no longer needed
+  C* Pii = fac + tile_index(i, i) * TILE_ELEMS;
+  if (j == 0) {
+    const double2 lam = lambda[n];
+    for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) {
+      const int c = e >> 6, r = e & 63;
+      const double2 b = shifted_entry(g, coef, lam, M, i * TILE + r, i * TILE + c);
+      S[c * LDSLD + r] = cmk<C>((R)b.x, (R)b.y);
+    }
+  } else {
+    for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) S[(e >> 6) * LDSLD + (e & 63)] = Pii[e];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
+          const int c = wc * 32 + bj * 16 + l16;
+          S[c * LDSLD + r] = csub(S[c * LDSLD + r], cmk<C>(dl.re[bi][bj][e], dl.im[bi][bj][e]));
+        }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) Pii[e] = S[(e >> 6) * LDSLD + (e & 63)];
 }
 
 template <typename C>
@@ -332,17 +402,32 @@ __global__ void __launch_bounds__(256) k_trsv(const C* __restrict__ factors, siz
   const int Mp = T * TILE;
   for (int r = t; r < Mp; r += 256) xs[r] = (r < M) ? zin[(size_t)n * M + r] : cmk<C>((R)0, (R)0);
   __syncthreads();
-  // forward
+  // forward.  The off-diagonal tiles of tile row i are contiguous (tile index i(i+1)/2 + k), so
+  // two consecutive tiles are fetched together to keep 32 loads per lane in flight.
   for (int i = 0; i < T; ++i) {
-    C acc = cmk<C>((R)0, (R)0);
-    for (int k = 0; k < i; ++k) {
-      const C* Lik = fac + tile_index(i, k) * TILE_ELEMS;
+    C acc = cmk<C>((R)0, (R)0), acc1 = cmk<C>((R)0, (R)0);
+    const C* Lrow = fac + tile_index(i, 0) * TILE_ELEMS + (16 * w) * TILE + lane;
+    int k = 0;
+    for (; k + 1 < i; k += 2) {
+      const C* L0 = Lrow + (size_t)k * TILE_ELEMS;
+      C a0[16], a1[16];
 #pragma unroll
       for (int cc = 0; cc < 16; ++cc) {
-        const int c = 16 * w + cc;
-        acc = cadd(acc, cmul(Lik[c * TILE + lane], xs[k * TILE + c]));
+        a0[cc] = L0[cc * TILE];
+        a1[cc] = L0[TILE_ELEMS + cc * TILE];
+      }
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) {
+        acc = cadd(acc, cmul(a0[cc], xs[k * TILE + 16 * w + cc]));
+        acc1 = cadd(acc1, cmul(a1[cc], xs[(k + 1) * TILE + 16 * w + cc]));
       }
     }
+    if (k < i) {
+      const C* L0 = Lrow + (size_t)k * TILE_ELEMS;
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) acc = cadd(acc, cmul(L0[cc * TILE], xs[k * TILE + 16 * w + cc]));
+    }
+    acc = cadd(acc, acc1);
     red[w][lane] = acc;
     __syncthreads();
     if (w == 0) {
@@ -378,11 +463,25 @@ __global__ void __launch_bounds__(256) k_trsv(const C* __restrict__ factors, siz
     C acc[16];
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) acc[cc] = cmk<C>((R)0, (R)0);
-    for (int i = k + 1; i < T; ++i) {
-      const C* Lik = fac + tile_index(i, k) * TILE_ELEMS;
-      const C xi = xs[i * TILE + lane];
+    int i = k + 1;
+    for (; i + 1 < T; i += 2) {
+      const C* L0 = fac + tile_index(i, k) * TILE_ELEMS + (16 * w) * TILE + lane;
+      const C* L1 = fac + tile_index(i + 1, k) * TILE_ELEMS + (16 * w) * TILE + lane;
+      C a0[16], a1[16];
 #pragma unroll
-      for (int cc = 0; cc < 16; ++cc) acc[cc] = cadd(acc[cc], cmul(Lik[(16 * w + cc) * TILE + lane], xi));
+      for (int cc = 0; cc < 16; ++cc) {
+        a0[cc] = L0[cc * TILE];
+        a1[cc] = L1[cc * TILE];
+      }
+      const C x0 = xs[i * TILE + lane], x1 = xs[(i + 1) * TILE + lane];
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) acc[cc] = cadd(acc[cc], cadd(cmul(a0[cc], x0), cmul(a1[cc], x1)));
+    }
+    if (i < T) {
+      const C* L0 = fac + tile_index(i, k) * TILE_ELEMS + (16 * w) * TILE + lane;
+      const C x0 = xs[i * TILE + lane];
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) acc[cc] = cadd(acc[cc], cmul(L0[cc * TILE], x0));
     }
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {

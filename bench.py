@@ -112,6 +112,8 @@ def measure_form(bits, args, W, alphas, inputs, dev):
     y = torch.empty_like(v)
     p.apply_A(v, out=y)
     ms_mv = event_ms(lambda: p.apply_A(v, out=y), 20, s)
+    ms_a = event_ms(lambda: p.step_a(v), 20, s)
+    ms_c = event_ms(lambda: p.step_c(z1), 20, s)
     p.destroy()
 
     fp32 = bits == 32
@@ -124,9 +126,26 @@ def measure_form(bits, args, W, alphas, inputs, dev):
     bytes_b = nf * float(M) * M * esz
     # step (b) is timed through the C ABI; for FP32 plans that call also converts c128 <-> c64
     # around the solves (about 0.1% of its bytes at this size).
+    N = float(Nt) * M
+    nfS = float(nf) * M
+    csz = 8 if fp32 else 16
+
+    def hbm(nbytes, ms):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"ms": round(ms, 5), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+
+    kernels = {
+        # a6: read v, write y (16 B per unknown)
+        "matvec (a6)": hbm(16 * N, ms_mv),
+        # a7: read v (8 B per unknown), write the half spectrum (csz B per entry); through the
+        # C ABI an FP32 plan also widens the output to c128
+        "step a (a7)": hbm(8 * N + csz * nfS, ms_a),
+        # a9: read the half spectrum, write v
+        "step c (a9)": hbm(csz * nfS + 8 * N, ms_c),
+    }
     return dict(
         value=float(np.mean([r["ms_total"] for r in recs])), ms_per_step=ms_per_step, recs=recs,
-        sols=sols, ms_pinv=ms_pinv, ms_stepb=ms_stepb, ms_mv=ms_mv, info=info,
+        sols=sols, ms_pinv=ms_pinv, ms_stepb=ms_stepb, ms_mv=ms_mv, info=info, kernels=kernels,
         roofline={"kernel": "k_ldlt_diag+k_ldlt_panel (factorisation)", "bound": "mfma",
                   "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                   "frac": round(achieved / peak, 4), "traffic": None},
@@ -224,6 +243,7 @@ def main():
         "per_solve": [{k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r.items()
                        if k in ("alpha", "ms_total", "ms_setup", "ms_factor", "ms_solve", "iters",
                                 "true_rel_res")} for r in base["recs"]],
+        "hbm_kernels": base["kernels"],
         "roofline": base["roofline"],
         "roofline_step_b": base["roofline_step_b"],
         "forms": forms_out,

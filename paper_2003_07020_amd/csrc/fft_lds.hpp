@@ -111,81 +111,106 @@ __host__ __device__ constexpr int pass_radix(int N, int Ns) {
   return (N / Ns) >= 16 ? 16 : (N / Ns);
 }
 
-// One Stockham pass over `nb` batched transforms stored back to back in `buf` (stride N).
-// All NT threads of the block participate; includes the two barriers.
-template <int N, int R, int SIGN, int NT, int NB, typename C>
-__device__ __forceinline__ void stockham_pass(C* buf, int Ns, const C* __restrict__ tw) {
+// Placeholder functors for passes that stay inside LDS.
+struct NoLoad {};
+struct NoStore {};
+
+// One Stockham pass over NB batched transforms held in LDS (transform f at buf + f * LDN).
+//   FIRST: the pass reads its inputs through load(f, idx) instead of from buf (no LDS read);
+//   LAST:  the pass hands its outputs to store(f, idx, value) instead of writing buf.
+//   BFAST: consecutive threads take consecutive transforms (batch index fastest), which makes
+//          strided global loads/stores of the FIRST/LAST passes coalesced when the transforms
+//          are adjacent columns of a row-major array; LDN should then be odd (N + 1).
+// Twiddles: w = tw[k * step] is read once per butterfly (tw[m] = exp(-2 pi i m / N)) and its
+// powers w^t are formed by repeated multiplication.
+// Barriers: after the reads when they came from buf (the pass is in place), and after the
+// writes when they went to buf.  A caller must synchronise before reusing buf after a LAST
+// pass whose store writes buf.
+template <int N, int R, int Ns, int SIGN, int NT, int NB, int LDN, bool BFAST, bool FIRST,
+          bool LAST, typename C, typename Load, typename Store>
+__device__ __forceinline__ void stockham_pass_io(C* buf, const C* __restrict__ tw, Load& load,
+                                                 Store& store) {
   constexpr int NBF = N / R;               // butterflies per transform
   constexpr int TOT = NBF * NB;            // butterflies in the block
   constexpr int BPT = (TOT + NT - 1) / NT; // butterflies per thread
+  constexpr int step = N / (Ns * R);
   C v[BPT][R];
   const int tid = threadIdx.x;
-  const int step = N / (Ns * R);
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int jj = tid + b * NT;
     if (TOT % NT == 0 || jj < TOT) {
-      const int f = jj / NBF, j = jj - f * NBF;
-      const int k = j % Ns;
-      C* src = buf + f * N;
+      const int f = BFAST ? jj % NB : jj / NBF;
+      const int j = BFAST ? jj / NB : jj - f * NBF;
+      const int k = j & (Ns - 1);
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[b][t] = src[j + t * NBF];
-      if (Ns > 1) {
+      for (int t = 0; t < R; ++t) {
+        if constexpr (FIRST) v[b][t] = load(f, j + t * NBF);
+        else v[b][t] = buf[f * LDN + j + t * NBF];
+      }
+      if constexpr (Ns > 1) {
+        C w = tw[k * step];
+        if (SIGN > 0) w = cconj(w);
+        C wt = w;
+        v[b][1] = cmul(v[b][1], wt);
 #pragma unroll
-        for (int t = 1; t < R; ++t) {
-          C w = tw[t * k * step];
-          if (SIGN > 0) w = cconj(w);
-          v[b][t] = cmul(v[b][t], w);
+        for (int t = 2; t < R; ++t) {
+          wt = cmul(wt, w);
+          v[b][t] = cmul(v[b][t], wt);
         }
       }
       dft_r<R, SIGN>(v[b]);
     }
   }
-  __syncthreads();
+  if constexpr (!FIRST) __syncthreads();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int jj = tid + b * NT;
     if (TOT % NT == 0 || jj < TOT) {
-      const int f = jj / NBF, j = jj - f * NBF;
-      const int k = j % Ns;
-      C* dst = buf + f * N;
+      const int f = BFAST ? jj % NB : jj / NBF;
+      const int j = BFAST ? jj / NB : jj - f * NBF;
+      const int k = j & (Ns - 1);
       const int idxD = (j / Ns) * Ns * R + k;
 #pragma unroll
-      for (int t = 0; t < R; ++t) dst[idxD + t * Ns] = v[b][t];
-    }
-  }
-  __syncthreads();
-}
-
-// Full length-N transform of NB batched sequences held in LDS (natural order in and out).
-// The caller must __syncthreads() after filling buf.
-template <int N, int SIGN, int NT, int NB, typename C>
-__device__ __forceinline__ void fft_lds(C* buf, const C* __restrict__ tw) {
-  if constexpr (N >= 2) {
-    constexpr int R0 = pass_radix(N, 1);
-    stockham_pass<N, R0, SIGN, NT, NB>(buf, 1, tw);
-    if constexpr (N / R0 >= 2) {
-      constexpr int Ns1 = R0;
-      constexpr int R1 = pass_radix(N, Ns1);
-      stockham_pass<N, R1, SIGN, NT, NB>(buf, Ns1, tw);
-      if constexpr (N / (Ns1 * R1) >= 2) {
-        constexpr int Ns2 = Ns1 * R1;
-        constexpr int R2 = pass_radix(N, Ns2);
-        stockham_pass<N, R2, SIGN, NT, NB>(buf, Ns2, tw);
-        if constexpr (N / (Ns2 * R2) >= 2) {
-          constexpr int Ns3 = Ns2 * R2;
-          constexpr int R3 = pass_radix(N, Ns3);
-          stockham_pass<N, R3, SIGN, NT, NB>(buf, Ns3, tw);
-          if constexpr (N / (Ns3 * R3) >= 2) {
-            constexpr int Ns4 = Ns3 * R3;
-            constexpr int R4 = pass_radix(N, Ns4);
-            stockham_pass<N, R4, SIGN, NT, NB>(buf, Ns4, tw);
-            static_assert(N / (Ns4 * R4) < 2, "FFT length beyond 16^5");
-          }
-        }
+      for (int t = 0; t < R; ++t) {
+        if constexpr (LAST) store(f, idxD + t * Ns, v[b][t]);
+        else buf[f * LDN + idxD + t * Ns] = v[b][t];
       }
     }
   }
+  if constexpr (!LAST) __syncthreads();
+}
+
+template <int N, int Ns, int SIGN, int NT, int NB, int LDN, bool BFAST, bool FIRST_EXT,
+          bool LAST_EXT, typename C, typename Load, typename Store>
+__device__ __forceinline__ void fft_passes(C* buf, const C* __restrict__ tw, Load& load,
+                                           Store& store) {
+  constexpr int R = pass_radix(N, Ns);
+  constexpr bool last = (Ns * R >= N);
+  stockham_pass_io<N, R, Ns, SIGN, NT, NB, LDN, BFAST, FIRST_EXT && Ns == 1, LAST_EXT && last>(
+      buf, tw, load, store);
+  if constexpr (!last) {
+    fft_passes<N, Ns * R, SIGN, NT, NB, LDN, BFAST, FIRST_EXT, LAST_EXT>(buf, tw, load, store);
+  } else if constexpr (!LAST_EXT) {
+    // the final pass wrote buf and synchronised
+  }
+}
+
+// Length-N transform of NB sequences, first inputs from load(f, idx) (or buf), last outputs to
+// store(f, idx, value) (or buf, natural order).  N must be a power of two >= 2.
+template <int N, int SIGN, int NT, int NB, int LDN, bool BFAST, bool FIRST_EXT, bool LAST_EXT,
+          typename C, typename Load, typename Store>
+__device__ __forceinline__ void fft_io(C* buf, const C* __restrict__ tw, Load& load, Store& store) {
+  fft_passes<N, 1, SIGN, NT, NB, LDN, BFAST, FIRST_EXT, LAST_EXT>(buf, tw, load, store);
+}
+
+// Full length-N transform of NB batched sequences held in LDS (natural order in and out,
+// transform f at buf + f * N).  The caller must __syncthreads() after filling buf.
+template <int N, int SIGN, int NT, int NB, typename C>
+__device__ __forceinline__ void fft_lds(C* buf, const C* __restrict__ tw) {
+  NoLoad nl;
+  NoStore ns;
+  fft_passes<N, 1, SIGN, NT, NB, N, false, false, false>(buf, tw, nl, ns);
 }
 
 }  // namespace rfde

@@ -22,121 +22,124 @@ __device__ __forceinline__ C dst_coef(C y, typename cplx_traits<C>::real sc) {
 
 // Rows: `nrows` contiguous rows of length n; NB rows per block.  DST along the row; with
 // SCALE, divide coefficient k by (lambda_f + coef sigma_k) and apply the DST again
-// (f = row / rows_per_freq).
-template <int P, int NB, typename C, bool SCALE>
-__global__ void __launch_bounds__(256) k_dst_rows(C* __restrict__ z, int nrows, int rows_per_freq,
-                                                  const double2* __restrict__ lambda,
-                                                  const double* __restrict__ sigma, double coef,
-                                                  const C* __restrict__ tw) {
+// (f = row / rows_per_freq).  The odd extension is formed by the first FFT pass's loads and the
+// coefficients are written by the last pass's stores.
+template <int P, int NB, int NT, typename C, bool SCALE>
+__global__ void __launch_bounds__(NT) k_dst_rows(C* __restrict__ z, int nrows, int rows_per_freq,
+                                                 const double2* __restrict__ lambda,
+                                                 const double* __restrict__ sigma, double coef,
+                                                 const C* __restrict__ tw) {
   using R = typename cplx_traits<C>::real;
   constexpr int n = P / 2 - 1;
   __shared__ C buf[NB * P];
   const int row0 = blockIdx.x * NB;
   const R sc = (R)sqrt(2.0 / (n + 1));
-  for (int e = threadIdx.x; e < NB * (n + 2); e += 256) {
-    const int b = e / (n + 2), j = e - b * (n + 2);
-    const int row = row0 + b;
-    C* B = buf + b * P;
-    if (j == 0 || j == n + 1 || row >= nrows) {
-      B[j] = cmk<C>((R)0, (R)0);
-      if (j > 0 && j <= n) B[P - j] = cmk<C>((R)0, (R)0);
-    } else {
-      const C x = z[(size_t)row * n + j - 1];
-      B[j] = x;
-      B[P - j] = cmk<C>(-x.x, -x.y);
-    }
-  }
-  __syncthreads();
-  fft_lds<P, -1, 256, NB>(buf, tw);
+  auto load = [&](int f, int idx) -> C {
+    const int row = row0 + f;
+    if (row >= nrows || idx == 0 || idx == n + 1) return cmk<C>((R)0, (R)0);
+    if (idx <= n) return z[(size_t)row * n + idx - 1];
+    const C x = z[(size_t)row * n + (P - idx) - 1];
+    return cmk<C>(-x.x, -x.y);
+  };
+  auto store_out = [&](int f, int idx, C y) {
+    const int row = row0 + f;
+    if (row < nrows && idx >= 1 && idx <= n) z[(size_t)row * n + idx - 1] = dst_coef(y, sc);
+  };
   if constexpr (SCALE) {
-    for (int e = threadIdx.x; e < NB * n; e += 256) {
-      const int b = e / n, k = e - b * n + 1;
-      const int row = row0 + b;
-      C* B = buf + b * P;
-      C wv = dst_coef(B[k], sc);
-      if (row < nrows) {
-        const double2 lam = lambda[row / rows_per_freq];
-        const double dr = lam.x + coef * sigma[k - 1], di = lam.y;
-        const double den = dr * dr + di * di;
-        wv = cmul(wv, cmk<C>((R)(dr / den), (R)(-di / den)));
+    auto store_scaled = [&](int f, int idx, C y) {
+      const int row = row0 + f;
+      C* B = buf + f * P;
+      if (idx == 0 || idx == n + 1) {
+        B[idx] = cmk<C>((R)0, (R)0);
+      } else if (idx <= n) {
+        C wv = cmk<C>((R)0, (R)0);
+        if (row < nrows) {
+          const double2 lam = lambda[row / rows_per_freq];
+          const double dr = lam.x + coef * sigma[idx - 1], di = lam.y;
+          const double den = dr * dr + di * di;
+          wv = cmul(dst_coef(y, sc), cmk<C>((R)(dr / den), (R)(-di / den)));
+        }
+        B[idx] = wv;
+        B[P - idx] = cmk<C>(-wv.x, -wv.y);
       }
-      B[k] = wv;
-      B[P - k] = cmk<C>(-wv.x, -wv.y);
-      if (k == 1) { B[0] = cmk<C>((R)0, (R)0); B[n + 1] = cmk<C>((R)0, (R)0); }
-    }
+    };
+    fft_io<P, -1, NT, NB, P, false, true, true>(buf, tw, load, store_scaled);
     __syncthreads();
-    fft_lds<P, -1, 256, NB>(buf, tw);
-  }
-  for (int e = threadIdx.x; e < NB * n; e += 256) {
-    const int b = e / n, k = e - b * n + 1;
-    const int row = row0 + b;
-    if (row < nrows) z[(size_t)row * n + k - 1] = dst_coef(buf[b * P + k], sc);
+    NoLoad nl;
+    fft_io<P, -1, NT, NB, P, false, false, true>(buf, tw, nl, store_out);
+  } else {
+    fft_io<P, -1, NT, NB, P, false, true, true>(buf, tw, load, store_out);
   }
 }
 
-// Columns of [nf][My][Mx] planes: one block per (frequency, tile of NB columns).  DST along y,
-// divide by lambda_n + coef_x sigma^x_ix + coef_y sigma^y_iy (the x-direction DST has already
-// been applied to the rows), DST along y again.
-template <int P, int NB, typename C>
-__global__ void __launch_bounds__(256) k_dst_cols(C* __restrict__ z, int Mx,
-                                                  const double2* __restrict__ lambda,
-                                                  const double* __restrict__ sigx,
-                                                  const double* __restrict__ sigy, double cx,
-                                                  double cy, const C* __restrict__ tw) {
+// Columns of [nf][My][Mx] planes: one block per (frequency, tile of NB columns), columns taken
+// fastest by the threads.  DST along y, divide by lambda_n + coef_x sigma^x_ix +
+// coef_y sigma^y_iy (the x-direction DST has already been applied to the rows), DST again.
+template <int P, int NB, int NT, typename C>
+__global__ void __launch_bounds__(NT) k_dst_cols(C* __restrict__ z, int Mx,
+                                                 const double2* __restrict__ lambda,
+                                                 const double* __restrict__ sigx,
+                                                 const double* __restrict__ sigy, double cx,
+                                                 double cy, const C* __restrict__ tw) {
   using R = typename cplx_traits<C>::real;
   constexpr int n = P / 2 - 1;  // My
-  __shared__ C buf[NB * P];
+  constexpr int LDN = P + 1;
+  __shared__ C buf[NB * LDN];
   const int ntile = (Mx + NB - 1) / NB;
-  const int f = blockIdx.x / ntile, x0 = (blockIdx.x % ntile) * NB;
-  C* plane = z + (size_t)f * n * Mx;
+  const int fq = blockIdx.x / ntile, x0 = (blockIdx.x % ntile) * NB;
+  C* plane = z + (size_t)fq * n * Mx;
   const R sc = (R)sqrt(2.0 / (n + 1));
-  for (int e = threadIdx.x; e < NB * P; e += 256) buf[e] = cmk<C>((R)0, (R)0);
-  __syncthreads();
-  for (int e = threadIdx.x; e < n * NB; e += 256) {
-    const int iy = e / NB, b = e - iy * NB, x = x0 + b;
-    if (x < Mx) {
-      const C v = plane[(size_t)iy * Mx + x];
-      buf[b * P + iy + 1] = v;
-      buf[b * P + P - iy - 1] = cmk<C>(-v.x, -v.y);
+  const double2 lam = lambda[fq];
+  auto load = [&](int b, int idx) -> C {
+    const int x = x0 + b;
+    if (x >= Mx || idx == 0 || idx == n + 1) return cmk<C>((R)0, (R)0);
+    if (idx <= n) return plane[(size_t)(idx - 1) * Mx + x];
+    const C v = plane[(size_t)(P - idx - 1) * Mx + x];
+    return cmk<C>(-v.x, -v.y);
+  };
+  auto store_scaled = [&](int b, int idx, C y) {
+    const int x = x0 + b;
+    C* B = buf + b * LDN;
+    if (idx == 0 || idx == n + 1) {
+      B[idx] = cmk<C>((R)0, (R)0);
+    } else if (idx <= n) {
+      C wv = cmk<C>((R)0, (R)0);
+      if (x < Mx) {
+        const double dr = lam.x + cx * sigx[x] + cy * sigy[idx - 1], di = lam.y;
+        const double den = dr * dr + di * di;
+        wv = cmul(dst_coef(y, sc), cmk<C>((R)(dr / den), (R)(-di / den)));
+      }
+      B[idx] = wv;
+      B[P - idx] = cmk<C>(-wv.x, -wv.y);
     }
-  }
+  };
+  fft_io<P, -1, NT, NB, LDN, true, true, true>(buf, tw, load, store_scaled);
   __syncthreads();
-  fft_lds<P, -1, 256, NB>(buf, tw);
-  const double2 lam = lambda[f];
-  for (int e = threadIdx.x; e < NB * n; e += 256) {
-    const int b = e / n, k = e - b * n + 1, x = x0 + b;
-    C* B = buf + b * P;
-    C wv = dst_coef(B[k], sc);
-    if (x < Mx) {
-      const double dr = lam.x + cx * sigx[x] + cy * sigy[k - 1], di = lam.y;
-      const double den = dr * dr + di * di;
-      wv = cmul(wv, cmk<C>((R)(dr / den), (R)(-di / den)));
-    } else {
-      wv = cmk<C>((R)0, (R)0);
-    }
-    B[k] = wv;
-    B[P - k] = cmk<C>(-wv.x, -wv.y);
-    if (k == 1) { B[0] = cmk<C>((R)0, (R)0); B[n + 1] = cmk<C>((R)0, (R)0); }
-  }
-  __syncthreads();
-  fft_lds<P, -1, 256, NB>(buf, tw);
-  for (int e = threadIdx.x; e < n * NB; e += 256) {
-    const int iy = e / NB, b = e - iy * NB, x = x0 + b;
-    if (x < Mx) plane[(size_t)iy * Mx + x] = dst_coef(buf[b * P + iy + 1], sc);
-  }
+  auto store_out = [&](int b, int idx, C y) {
+    const int x = x0 + b;
+    if (x < Mx && idx >= 1 && idx <= n) plane[(size_t)(idx - 1) * Mx + x] = dst_coef(y, sc);
+  };
+  NoLoad nl;
+  fft_io<P, -1, NT, NB, LDN, true, false, true>(buf, tw, nl, store_out);
 }
 
 template <int P, typename C>
 constexpr int dst_nb() {
-  constexpr int cap = 65536 / (P * (int)sizeof(C));
-  return cap < 1 ? 1 : (cap > 16 ? 16 : cap);
+  constexpr int target = (int)sizeof(C) == 16 ? 8 : 16;
+  constexpr int cap = 135168 / ((P + 1) * (int)sizeof(C));
+  return cap < 1 ? 1 : (cap < target ? cap : target);
+}
+template <int P, typename C>
+constexpr int dst_nt() {
+  return dst_nb<P, C>() * P >= 4096 ? 512 : 256;
 }
 
 template <int P, typename C, bool SCALE>
 static int dst_rows(const Plan& p, C* z, int nrows, int rows_per_freq, const double* sigma,
                     double coef, const C* tw) {
   constexpr int NB = dst_nb<P, C>();
-  k_dst_rows<P, NB, C, SCALE><<<(nrows + NB - 1) / NB, 256, 0, p.stream>>>(
+  constexpr int NT = dst_nt<P, C>();
+  k_dst_rows<P, NB, NT, C, SCALE><<<(nrows + NB - 1) / NB, NT, 0, p.stream>>>(
       z, nrows, rows_per_freq, p.lambda, sigma, coef, tw);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
@@ -145,9 +148,11 @@ static int dst_rows(const Plan& p, C* z, int nrows, int rows_per_freq, const dou
 template <int P, typename C>
 static int dst_cols(const Plan& p, C* z, const C* tw) {
   constexpr int NB = dst_nb<P, C>();
+  constexpr int NT = dst_nt<P, C>();
   const int ntile = (p.Mx + NB - 1) / NB;
-  k_dst_cols<P, NB, C><<<p.nf * ntile, 256, 0, p.stream>>>(z, p.Mx, p.lambda, p.sigma,
-                                                           p.sigma + p.Mx, p.coef_x, p.coef_y, tw);
+  k_dst_cols<P, NB, NT, C><<<p.nf * ntile, NT, 0, p.stream>>>(z, p.Mx, p.lambda, p.sigma,
+                                                              p.sigma + p.Mx, p.coef_x, p.coef_y,
+                                                              tw);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

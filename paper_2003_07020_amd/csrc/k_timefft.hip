@@ -5,41 +5,42 @@
 // step (c): v_j = (1 / (Nt s_j)) sum_n theta^{-n j} z2_n with z2_{Nt-n} = conj(z2_n).
 //
 // Layout: v is [Nt][S] (space fastest), z is [Nt/2+1][S] complex.  A block owns a tile of
-// TS = 2 NB adjacent spatial points and all Nt time levels; two real sequences (points 2p and
-// 2p+1 of the tile) share one complex transform, and are separated with the conjugate-symmetry
+// TS = 2 NB adjacent spatial points and all Nt time levels.  Two real sequences (points 2p and
+// 2p+1 of the tile) share one complex transform and are separated with the conjugate symmetry
 // of real-input DFTs: X = (Z_n + conj(Z_{Nt-n})) / 2, Y = (Z_n - conj(Z_{Nt-n})) / (2i).
+// Threads take the NB transforms fastest, so every global access is a contiguous row segment
+// of TS values (128 bytes where the LDS budget allows); the first pass of step (a) reads v
+// straight from memory and the last pass of step (c) writes v straight to memory.
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"
 
 namespace rfde {
 
-template <typename C> __device__ __forceinline__ C from_d2(double2 a) {
-  return cmk<C>((typename cplx_traits<C>::real)a.x, (typename cplx_traits<C>::real)a.y);
-}
-
-template <int N, int NB, typename C>
-__global__ void __launch_bounds__(256) k_time_fwd(const double* __restrict__ v, C* __restrict__ z1,
-                                                  const double* __restrict__ s,
-                                                  const C* __restrict__ tw, int S) {
+template <int N, int NB, int NT, typename C>
+__global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C* __restrict__ z1,
+                                                 const double* __restrict__ s,
+                                                 const C* __restrict__ tw, int S) {
   using R = typename cplx_traits<C>::real;
-  __shared__ C buf[NB * N];
+  constexpr int LDN = N + 1;
+  __shared__ C buf[NB * LDN];
   constexpr int TS = 2 * NB;
   const int i0 = blockIdx.x * TS;
-  for (int e = threadIdx.x; e < N * TS; e += 256) {
-    const int j = e / TS, q = e - j * TS;
-    const int i = i0 + q;
-    const R val = (i < S) ? (R)(s[j] * v[(size_t)j * S + i]) : (R)0;
-    R* slot = reinterpret_cast<R*>(&buf[(q >> 1) * N + j]);
-    slot[q & 1] = val;
-  }
-  __syncthreads();
-  fft_lds<N, +1, 256, NB>(buf, tw);
-  for (int e = threadIdx.x; e < (N / 2 + 1) * TS; e += 256) {
+  auto load = [&](int f, int j) -> C {
+    const int i = i0 + 2 * f;
+    const double* row = v + (size_t)j * S;
+    const double sj = s[j];
+    const R a = (i < S) ? (R)(sj * row[i]) : (R)0;
+    const R b = (i + 1 < S) ? (R)(sj * row[i + 1]) : (R)0;
+    return cmk<C>(a, b);
+  };
+  NoStore ns;
+  fft_io<N, +1, NT, NB, LDN, true, true, false>(buf, tw, load, ns);
+  for (int e = threadIdx.x; e < (N / 2 + 1) * TS; e += NT) {
     const int n = e / TS, q = e - n * TS;
     const int i = i0 + q;
     if (i >= S) continue;
-    const C a = buf[(q >> 1) * N + n];
-    const C b = cconj(buf[(q >> 1) * N + ((N - n) & (N - 1))]);
+    const C a = buf[(q >> 1) * LDN + n];
+    const C b = cconj(buf[(q >> 1) * LDN + ((N - n) & (N - 1))]);
     C out;
     if ((q & 1) == 0) out = cmk<C>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y + b.y));
     else out = cmk<C>((R)0.5 * (a.y - b.y), (R)-0.5 * (a.x - b.x));
@@ -47,55 +48,65 @@ __global__ void __launch_bounds__(256) k_time_fwd(const double* __restrict__ v, 
   }
 }
 
-template <int N, int NB, typename C>
-__global__ void __launch_bounds__(256) k_time_inv(const C* __restrict__ z2, double* __restrict__ v,
-                                                  const double* __restrict__ s,
-                                                  const C* __restrict__ tw, int S) {
+template <int N, int NB, int NT, typename C>
+__global__ void __launch_bounds__(NT) k_time_inv(const C* __restrict__ z2, double* __restrict__ v,
+                                                 const double* __restrict__ s,
+                                                 const C* __restrict__ tw, int S) {
   using R = typename cplx_traits<C>::real;
-  __shared__ C buf[NB * N];
+  constexpr int LDN = N + 1;
+  __shared__ C buf[NB * LDN];
   constexpr int TS = 2 * NB;
   const int i0 = blockIdx.x * TS;
-  for (int e = threadIdx.x; e < (N / 2 + 1) * NB; e += 256) {
-    const int n = e / NB, pp = e - n * NB;
-    const int ia = i0 + 2 * pp, ib = ia + 1;
+  // Z_n = P_n + i Q_n with P, Q the half spectra of points 2p, 2p+1, extended by
+  // P_{N-n} = conj(P_n); imaginary parts at n = 0 and n = N/2 are dropped.
+  auto load = [&](int f, int n) -> C {
+    const int ia = i0 + 2 * f, ib = ia + 1;
+    const int nn = n <= N / 2 ? n : N - n;
     C P = cmk<C>((R)0, (R)0), Q = cmk<C>((R)0, (R)0);
-    if (ia < S) P = z2[(size_t)n * S + ia];
-    if (ib < S) Q = z2[(size_t)n * S + ib];
-    if (n == 0 || n == N / 2) { P.y = (R)0; Q.y = (R)0; }
-    buf[pp * N + n] = cmk<C>(P.x - Q.y, P.y + Q.x);
-    if (n > 0 && n < N / 2) buf[pp * N + N - n] = cmk<C>(P.x + Q.y, Q.x - P.y);
-  }
-  __syncthreads();
-  fft_lds<N, -1, 256, NB>(buf, tw);
-  for (int e = threadIdx.x; e < N * TS; e += 256) {
-    const int j = e / TS, q = e - j * TS;
-    const int i = i0 + q;
-    if (i >= S) continue;
-    const C c = buf[(q >> 1) * N + j];
-    const double val = (double)((q & 1) ? c.y : c.x);
-    v[(size_t)j * S + i] = val / ((double)N * s[j]);
-  }
+    if (ia < S) P = z2[(size_t)nn * S + ia];
+    if (ib < S) Q = z2[(size_t)nn * S + ib];
+    if (nn == 0 || nn == N / 2) { P.y = (R)0; Q.y = (R)0; }
+    if (n <= N / 2) return cmk<C>(P.x - Q.y, P.y + Q.x);
+    return cmk<C>(P.x + Q.y, Q.x - P.y);
+  };
+  auto store = [&](int f, int j, C c) {
+    const int i = i0 + 2 * f;
+    double* row = v + (size_t)j * S;
+    const double sc = 1.0 / ((double)N * s[j]);
+    if (i < S) row[i] = (double)c.x * sc;
+    if (i + 1 < S) row[i + 1] = (double)c.y * sc;
+  };
+  fft_io<N, -1, NT, NB, LDN, true, true, true>(buf, tw, load, store);
 }
 
+// Transforms per block: 128-byte row segments (NB = 8 complex128 / 16 complex64 pairs) unless
+// the ~130 KB LDS budget forces fewer.
 template <int N, typename C>
 constexpr int time_nb() {
-  constexpr int cap = 65536 / (N * (int)sizeof(C));
-  return cap < 1 ? 1 : (cap > 16 ? 16 : cap);
+  constexpr int target = (int)sizeof(C) == 16 ? 8 : 16;
+  constexpr int cap = 135168 / ((N + 1) * (int)sizeof(C));
+  return cap < 1 ? 1 : (cap < target ? cap : target);
+}
+template <int N, typename C>
+constexpr int time_nt() {
+  return time_nb<N, C>() * N >= 4096 ? 512 : 256;
 }
 
 template <int N, typename C>
 static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw) {
   constexpr int NB = time_nb<N, C>();
+  constexpr int NT = time_nt<N, C>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_fwd<N, NB, C><<<blocks, 256, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S);
+  k_time_fwd<N, NB, NT, C><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
 template <int N, typename C>
 static int tf_inv(const Plan& p, const void* z2, double* v, const C* tw) {
   constexpr int NB = time_nb<N, C>();
+  constexpr int NT = time_nt<N, C>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_inv<N, NB, C><<<blocks, 256, 0, p.stream>>>((const C*)z2, v, p.s, tw, p.S);
+  k_time_inv<N, NB, NT, C><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw, p.S);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

@@ -76,9 +76,109 @@ template <typename C> struct WaveAcc {
   typename mma<C>::V re[2][2], im[2][2];
 };
 
-// acc = B_ij - sum_{k<j} (L_ik D_k) L_jk^T for the 64x64 tile (i, j) of block n.
+// acc = B_ij - sum_{k<j} (L_ik D_k) L_jk^T for the 64x64 tile (i, j) of block n, operands
+// staged through LDS (used for FP32).  The K dimension (j tiles of 64 columns) is walked in chunks of KC = 16 columns.  A chunk of
+// L_ik, of L_jk (16 contiguous tile columns each, column-major tiles) and the 16 matching d_k
+// are copied by the whole workgroup into one of two LDS buffers while the four waves run the
+// MFMAs of the previous chunk from the other buffer, so every operand byte crosses the
+// global-memory path once per workgroup instead of once per wave.
+constexpr int KC = 16;
+template <typename C> struct StageBuf {
+  C A[2][KC * TILE];
+  C B[2][KC * TILE];
+  C D[2][KC];
+};
+
 template <typename C>
-__device__ __forceinline__ void tile_update(WaveAcc<C>& acc, const C* __restrict__ fac, int i,
+__device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __restrict__ fac,
+                                                   int i, int j, const double* __restrict__ g,
+                                                   double coef, double2 lam, int M,
+                                                   StageBuf<C>& sb) {
+  using R = typename mma<C>::R;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
+        const int c = wc * 32 + bj * 16 + l16;
+        const double2 b = shifted_entry(g, coef, lam, M, i * TILE + r, j * TILE + c);
+        acc.re[bi][bj][e] = (R)b.x;
+        acc.im[bi][bj][e] = (R)b.y;
+      }
+  const int nchunk = j * (TILE / KC);
+  if (nchunk == 0) return;
+  // per thread: 4 entries of each operand chunk (KC*64 = 1024 = 4 x 256) and one d
+  const C* Arow = fac + tile_index(i, 0) * TILE_ELEMS;
+  const C* Brow = fac + tile_index(j, 0) * TILE_ELEMS;
+  C ra[4], rb[4], rd;
+  auto gload = [&](int c) {
+    const int k = c / (TILE / KC), c0 = (c % (TILE / KC)) * KC;
+    const size_t off = (size_t)k * TILE_ELEMS + (size_t)c0 * TILE;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ra[u] = Arow[off + tid + 256 * u];
+      rb[u] = Brow[off + tid + 256 * u];
+    }
+    if (tid < KC) rd = fac[tile_index(k, k) * TILE_ELEMS + (size_t)(c0 + tid) * (TILE + 1)];
+  };
+  auto lstore = [&](int bsel) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sb.A[bsel][tid + 256 * u] = ra[u];
+      sb.B[bsel][tid + 256 * u] = rb[u];
+    }
+    if (tid < KC) sb.D[bsel][tid] = rd;
+  };
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int cur = c & 1;
+    if (c + 1 < nchunk) gload(c + 1);
+#pragma unroll
+    for (int q = 0; q < KC / 4; ++q) {
+      const int kk = 4 * q + lq;
+      const C d = sb.D[cur][kk];
+      R nar[2], nai[2], nnai[2], br[2], bi_[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const C a = sb.A[cur][kk * TILE + wr * 32 + bi * 16 + l16];
+        // na = -(a d)
+        nar[bi] = -(a.x * d.x - a.y * d.y);
+        nai[bi] = -(a.x * d.y + a.y * d.x);
+        nnai[bi] = -nai[bi];
+      }
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const C b = sb.B[cur][kk * TILE + wc * 32 + bj * 16 + l16];
+        br[bj] = b.x;
+        bi_[bj] = b.y;
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          acc.re[bi][bj] = mma<C>::fma(nar[bi], br[bj], acc.re[bi][bj]);
+          acc.re[bi][bj] = mma<C>::fma(nnai[bi], bi_[bj], acc.re[bi][bj]);
+          acc.im[bi][bj] = mma<C>::fma(nar[bi], bi_[bj], acc.im[bi][bj]);
+          acc.im[bi][bj] = mma<C>::fma(nai[bi], br[bj], acc.im[bi][bj]);
+        }
+    }
+    if (c + 1 < nchunk) lstore(cur ^ 1);
+    __syncthreads();
+  }
+}
+
+// acc = B_ij - sum_{k<j} (L_ik D_k) L_jk^T, operands read by each wave straight from global
+// memory in the MFMA lane layout (used for FP64, whose MFMAs are slow enough to hide the loads).
+template <typename C>
+__device__ __forceinline__ void tile_update_direct(WaveAcc<C>& acc, const C* __restrict__ fac, int i,
                                             int j, const double* __restrict__ g, double coef,
                                             double2 lam, int M) {
   using R = typename mma<C>::R;
@@ -217,14 +317,23 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(C* __restrict__ factors, siz
                                                     double coef,
                                                     const double2* __restrict__ lambda, int M) {
   using R = typename mma<C>::R;
-  __shared__ C S[TILE * LDSLD];
+  // LDS: operand staging during the K loop, then the 64x64 tile S for the epilogue
+  constexpr size_t SB = sizeof(StageBuf<C>), ST = sizeof(C) * TILE * LDSLD;
+  __shared__ __align__(16) unsigned char smem[SB > ST ? SB : ST];
+  StageBuf<C>& sb = *reinterpret_cast<StageBuf<C>*>(smem);
+  C* S = reinterpret_cast<C*>(smem);
   const int per = T - 1 - j;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int n = lb / per, i = j + 1 + lb % per;
   C* fac = factors + (size_t)n * sys_elems;
   {
     WaveAcc<C> acc;
-    tile_update<C>(acc, fac, i, j, g, coef, lambda[n], M);
+    if constexpr (sizeof(C) == 8) {
+      tile_update_staged<C>(acc, fac, i, j, g, coef, lambda[n], M, sb);
+      __syncthreads();  // staging buffers are reused as S
+    } else {
+      tile_update_direct<C>(acc, fac, i, j, g, coef, lambda[n], M);
+    }
     acc_to_lds<C>(acc, S);
   }
   __syncthreads();

@@ -193,10 +193,68 @@ int rfde_apply_Pinv(rfde_plan plan, const double* v, double* z);
  * Steps (a5)-(a10): solve the all-at-once system with FGMRES(m) right-preconditioned by P_eps.
  * u0: [S], f: [N_t][S], U_init: [N_t][S] initial guess or NULL (zero), U: [N_t][S] output;
  * tol <= 0 uses the plan's opts.tol.  stats: host pointer or NULL.  Synchronous.
+ * A guess whose residual ||F - A U_init|| is not below ||F|| is discarded (zero start).
  * Returns OK, ENOTCONV (U = last iterate), ENAN (non-finite F or residual), EINVAL, EHIP.
  */
 int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* U_init,
                double* U, double tol, rfde_stats* stats);
+
+
+/* ------------------------------------------------------------------------------------------
+ * Learned initial guess (not in the paper; a growth direction of this library).
+ *
+ * Because the all-at-once solution (eq. (2.11)) is linear in the data, the solution for data
+ * u0 = sum_k a_k sin(k pi x), f = e^{-t} sum_k b_k sin(k pi x) is sum_k c_k G_k with G_k the
+ * solution for the k-th unit data component.  A small network predicts the G_k, in the first Ks
+ * sine modes of x, from the problem parameters:
+ *   phat = (p - mu)/sd; h1 = tanh(W1 phat + b1); h2 = tanh(W2 h1 + b2); g = W3t h2 + b3,
+ *   g = (G_1, ..., G_nsrc) each [Nt][Ks], NOUT = nsrc * Nt * Ks; loss = mean (g - y)^2.
+ * FP32 master weights; the output layer's products use a BF16 copy of W3t on BF16 MFMAs with
+ * FP32 accumulation.  All pointers are device pointers owned by the caller (contiguous,
+ * row-major: W1 [H1][Pin], W2 [H2][H1], W3t [NOUT][H2]).  Limits: 1 <= B <= 64, Pin <= 64,
+ * H1 <= 256, 16 <= H2 <= 256 with H2 % 16 == 0, NOUT % 16 == 0.  All calls are async on the
+ * given stream; `ws` is a device workspace of rfde_mlp_workspace_bytes(m, B) bytes.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+  int Pin, H1, H2, NOUT;
+  float *W1, *b1, *W2, *b2, *W3t, *b3;      /* FP32 parameters                             */
+  unsigned short* W3t_bf16;                 /* BF16 copy of W3t (kept in step by Adam)     */
+  float *mW1, *vW1, *mb1, *vb1, *mW2, *vW2, *mb2, *vb2, *mW3, *vW3, *mb3, *vb3; /* Adam     */
+  const float *mu, *sd;                     /* feature standardisation, Pin each           */
+} rfde_mlp;
+
+/* Workspace bytes needed for batch size B. */
+size_t rfde_mlp_workspace_bytes(const rfde_mlp* m, int B);
+
+/* g[B][NOUT] = network(feats[B][Pin]).  Errors: EINVAL on limits or NULL pointers. */
+int rfde_mlp_forward(const rfde_mlp* m, const float* feats, int B, float* g, void* ws,
+                     void* stream);
+
+/* Forward, loss (device float *loss), and the gradients of the loss in `grads` (flat FP32,
+ * order W1, b1, W2, b2, W3t, b3); parameters are not changed. */
+int rfde_mlp_grads(const rfde_mlp* m, const float* feats, const float* y, int B, float* g,
+                   float* grads, float* loss, void* ws, void* stream);
+
+/* One Adam step (lr, beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias correction with step t >= 1)
+ * on targets y[B][NOUT]; *loss receives the loss before the step.  Needs the Adam moments. */
+int rfde_mlp_train_step(const rfde_mlp* m, const float* feats, const float* y, int B, float* g,
+                        float lr, int t, float* loss, void* ws, void* stream);
+
+/* dst[i] = src[i] rounded to BF16 (round to nearest even), i < n (device). */
+int rfde_f32_to_bf16(size_t n, const float* src, unsigned short* dst, void* stream);
+
+/* S[i][s] = sin((s+1) pi (i+1) / (M+1)), i < M, s < Ks <= 256: the DST-I vectors (device). */
+int rfde_sine_table(int M, int Ks, double* S, void* stream);
+
+/* U[t][i] = sum_s (sum_k coef_scaled[k] g[k][t][s]) S[i][s]: the guess for data coefficients
+ * coef (coef_scaled = coef * per-component output scale), U: [Nt][M] FP64 (device). */
+int rfde_guess_assemble(int nsrc, int Nt, int Ks, int M, const float* g, const double* coef_scaled,
+                        const double* S, double* U, void* stream);
+
+/* Y[t][s] = factor (2/(M+1)) sum_i U[t][i] S[i][s]: the coefficients of U in the first Ks sine
+ * modes, times `factor` (training targets use 1/mode^2). */
+int rfde_project_sine(int Nt, int M, int Ks, const double* U, const double* S, double factor,
+                      float* Y, void* stream);
 
 #ifdef __cplusplus
 }

@@ -17,8 +17,9 @@ Modules
   precond    alpha-circulant preconditioner, Section 3.1 and 3.2, tau/DST variant eq. (3.9)
   krylov     flexible GMRES with right preconditioning (Section 4 solver settings)
   twod       2D model eq. (4.1), Kronecker-sum Jacobian eq. (4.2), tau approximation eq. (4.5)
+  mlp        the learned initial-guess network (forward, chain-rule gradients, Adam, sine basis)
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py against a
 closed form, an invariant, a brute-force computation or a value printed in the paper.
 """
-from . import weights, allatonce, precond, krylov, twod  # noqa: F401
+from . import weights, allatonce, precond, krylov, twod, mlp  # noqa: F401

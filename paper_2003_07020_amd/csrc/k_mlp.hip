@@ -1,0 +1,517 @@
+// Learned initial guess: forward, backward and Adam kernels of the guess network, the guess
+// assembly and the sine-mode projection used to build its training targets.
+//
+// Network (per sample): phat = (p - mu)/sd; h1 = tanh(W1 phat + b1); h2 = tanh(W2 h1 + b2);
+// g = W3t h2 + b3 with W3t [NOUT x H2].  The output layer is the large one (NOUT = nsrc Nt Ks,
+// 524288 at M = 1023, N_t = 512, Ks = 64); its two products run on BF16 MFMAs
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulate) with BF16 copies of W3t, h2 and dg, while the
+// weight gradient dW3t = dg^T h2 is formed in FP32 inside the Adam update.  Loss = mean (g - y)^2.
+#include <cmath>
+
+#include "rfde_internal.hpp"
+
+namespace rfde {
+
+typedef float mf4_t __attribute__((ext_vector_type(4)));
+typedef short ms4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  // round to nearest even
+  unsigned int u = __float_as_uint(f);
+  const unsigned int lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+
+// accumulator element e of lane l sits at row 4*(l/16) + e, column l%16 of the 16x16 block
+__device__ __forceinline__ int bf_row(int l, int e) { return 4 * (l >> 4) + e; }
+
+// ---- hidden layers: one block per sample -----------------------------------------------------
+__global__ void __launch_bounds__(256) k_mlp_hidden(const float* __restrict__ feats,
+                                                    const float* __restrict__ mu,
+                                                    const float* __restrict__ sd,
+                                                    const float* __restrict__ W1,
+                                                    const float* __restrict__ b1,
+                                                    const float* __restrict__ W2,
+                                                    const float* __restrict__ b2, int Pin, int H1,
+                                                    int H2, float* __restrict__ phat_out,
+                                                    float* __restrict__ h1, float* __restrict__ h2,
+                                                    unsigned short* __restrict__ h2b) {
+  __shared__ float ph[64];
+  __shared__ float a1[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  if (t < Pin) {
+    const float v = (feats[(size_t)b * Pin + t] - mu[t]) / sd[t];
+    ph[t] = v;
+    phat_out[(size_t)b * Pin + t] = v;
+  }
+  __syncthreads();
+  if (t < H1) {
+    float s = b1[t];
+    for (int q = 0; q < Pin; ++q) s = fmaf(W1[t * Pin + q], ph[q], s);
+    const float v = tanhf(s);
+    a1[t] = v;
+    h1[(size_t)b * H1 + t] = v;
+  }
+  __syncthreads();
+  if (t < H2) {
+    float s = b2[t];
+    for (int q = 0; q < H1; ++q) s = fmaf(W2[t * H1 + q], a1[q], s);
+    const float v = tanhf(s);
+    h2[(size_t)b * H2 + t] = v;
+    h2b[(size_t)b * H2 + t] = f2bf(v);
+  }
+}
+
+// ---- output layer: g[b][o] = sum_h h2[b][h] W3t[o][h] + b3[o] --------------------------------
+// One wave per 16 output columns and all batch rows (B <= 64, padded to 16-row blocks).
+template <int RB>
+__global__ void __launch_bounds__(256) k_mlp_out(const unsigned short* __restrict__ h2b,
+                                                 const unsigned short* __restrict__ W3b,
+                                                 const float* __restrict__ b3, int B, int H2,
+                                                 int NOUT, float* __restrict__ g) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int o0 = (blockIdx.x * 4 + w) * 16;
+  if (o0 >= NOUT) return;
+  const int l16 = lane & 15, lq = lane >> 4;
+  mf4_t acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = (mf4_t){0.f, 0.f, 0.f, 0.f};
+  const unsigned short* wrow = W3b + (size_t)(o0 + l16) * H2;
+  for (int k0 = 0; k0 < H2; k0 += 16) {
+    const int kk = k0 + 4 * lq;
+    ms4_t bv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bv[j] = (short)wrow[kk + j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int bb = r * 16 + l16;
+      ms4_t av;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) av[j] = bb < B ? (short)h2b[(size_t)bb * H2 + kk + j] : (short)0;
+      acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[r], 0, 0, 0);
+    }
+  }
+  const int o = o0 + l16;
+  const float bias = b3[o];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int bb = r * 16 + bf_row(lane, e);
+      if (bb < B) g[(size_t)bb * NOUT + o] = acc[r][e] + bias;
+    }
+}
+
+// ---- loss and dg ---------------------------------------------------------------------------------
+constexpr int MLP_RED = 1024;
+__global__ void __launch_bounds__(256) k_mlp_loss(const float* __restrict__ g,
+                                                  const float* __restrict__ y, size_t n,
+                                                  float* __restrict__ dg,
+                                                  unsigned short* __restrict__ dgb,
+                                                  double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const float scale = 2.0f / (float)n;
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)MLP_RED * 256) {
+    const float d = g[i] - y[i];
+    acc += (double)d * d;
+    const float gr = scale * d;
+    dg[i] = gr;
+    dgb[i] = f2bf(gr);
+  }
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void __launch_bounds__(256) k_mlp_loss_final(const double* __restrict__ partial,
+                                                        size_t n, float* __restrict__ loss) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < MLP_RED; b += 256) acc += partial[b];
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) loss[0] = (float)(((sh[0] + sh[1]) + (sh[2] + sh[3])) / (double)n);
+}
+
+// ---- dh2[b][h] = sum_o dg[b][o] W3t[o][h], split over chunks of KCH output columns -----------------
+constexpr int KCH = 1024;
+template <int RB>
+__global__ void __launch_bounds__(256) k_mlp_dh2(const unsigned short* __restrict__ dgb,
+                                                 const unsigned short* __restrict__ W3b, int B,
+                                                 int H2, int NOUT, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int c0 = blockIdx.x * KCH;
+  const int nhb = H2 / 16;
+  for (int hb = w; hb < nhb; hb += 4) {
+    mf4_t acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = (mf4_t){0.f, 0.f, 0.f, 0.f};
+    const int h = hb * 16 + l16;
+    for (int k0 = c0; k0 < c0 + KCH && k0 < NOUT; k0 += 16) {
+      const int kk = k0 + 4 * lq;
+      ms4_t bv;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = (short)W3b[(size_t)(kk + j) * H2 + h];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int bb = r * 16 + l16;
+        ms4_t av;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) av[j] = bb < B ? (short)dgb[(size_t)bb * NOUT + kk + j] : (short)0;
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[r], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int bb = r * 16 + bf_row(lane, e);
+        if (bb < B) part[((size_t)blockIdx.x * B + bb) * H2 + h] = acc[r][e];
+      }
+  }
+}
+
+__global__ void k_mlp_dh2_reduce(const float* __restrict__ part, int nchunk, int BH,
+                                 float* __restrict__ dh2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= BH) return;
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * BH + i];
+  dh2[i] = s;
+}
+
+// ---- Adam ----------------------------------------------------------------------------------------
+struct AdamCfg {
+  float lr, b1, b2, eps, c1, c2;  // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+};
+__device__ __forceinline__ void adam_apply(float& w, float& m, float& v, float grad,
+                                           const AdamCfg& a) {
+  m = a.b1 * m + (1.f - a.b1) * grad;
+  v = a.b2 * v + (1.f - a.b2) * grad * grad;
+  w -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+}
+
+// dW3t[o][h] = sum_b dg[b][o] h2[b][h] (FP32), db3[o] = sum_b dg[b][o]; Adam update of W3t and
+// its BF16 copy (mode 0) or plain gradient output (mode 1).
+__global__ void __launch_bounds__(256) k_mlp_w3(const float* __restrict__ dg,
+                                                const float* __restrict__ h2, int B, int H2,
+                                                int NOUT, float* __restrict__ W3t,
+                                                unsigned short* __restrict__ W3b,
+                                                float* __restrict__ mW, float* __restrict__ vW,
+                                                float* __restrict__ b3, float* __restrict__ mb,
+                                                float* __restrict__ vb, AdamCfg a, int mode,
+                                                float* __restrict__ gW, float* __restrict__ gb) {
+  const size_t total = (size_t)NOUT * H2;
+  const size_t e = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (e >= total) return;
+  const int o = (int)(e / H2), h = (int)(e % H2);
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) s = fmaf(dg[(size_t)b * NOUT + o], h2[(size_t)b * H2 + h], s);
+  if (mode == 1) {
+    gW[e] = s;
+  } else {
+    float w = W3t[e], m = mW[e], v = vW[e];
+    adam_apply(w, m, v, s, a);
+    W3t[e] = w; mW[e] = m; vW[e] = v;
+    W3b[e] = f2bf(w);
+  }
+  if (h == 0) {
+    float sb = 0.f;
+    for (int b = 0; b < B; ++b) sb += dg[(size_t)b * NOUT + o];
+    if (mode == 1) {
+      gb[o] = sb;
+    } else {
+      float w = b3[o], m = mb[o], v = vb[o];
+      adam_apply(w, m, v, sb, a);
+      b3[o] = w; mb[o] = m; vb[o] = v;
+    }
+  }
+}
+
+// Hidden layers backward from dh2, with Adam (mode 0) or gradient output (mode 1).  One block.
+struct SmallParams {
+  float *W1, *b1, *W2, *b2;
+  float *mW1, *vW1, *mb1, *vb1, *mW2, *vW2, *mb2, *vb2;
+  float *gW1, *gb1, *gW2, *gb2;
+};
+__global__ void __launch_bounds__(256) k_mlp_small_bwd(const float* __restrict__ phat,
+                                                       const float* __restrict__ h1,
+                                                       const float* __restrict__ h2,
+                                                       const float* __restrict__ dh2, int B,
+                                                       int Pin, int H1, int H2, SmallParams P,
+                                                       AdamCfg a, int mode,
+                                                       float* __restrict__ da2_ws,
+                                                       float* __restrict__ da1_ws) {
+  const int t = threadIdx.x;
+  // da2 = dh2 (1 - h2^2)
+  for (int e = t; e < B * H2; e += 256) da2_ws[e] = dh2[e] * (1.f - h2[e] * h2[e]);
+  __syncthreads();
+  // da1 = (da2 W2) (1 - h1^2) -- uses W2 before its update
+  for (int e = t; e < B * H1; e += 256) {
+    const int b = e / H1, q = e % H1;
+    float s = 0.f;
+    for (int r = 0; r < H2; ++r) s = fmaf(da2_ws[b * H2 + r], P.W2[r * H1 + q], s);
+    da1_ws[e] = s * (1.f - h1[e] * h1[e]);
+  }
+  __syncthreads();
+  for (int e = t; e < H2 * H1; e += 256) {
+    const int r = e / H1, q = e % H1;
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) s = fmaf(da2_ws[b * H2 + r], h1[b * H1 + q], s);
+    if (mode == 1) P.gW2[e] = s;
+    else adam_apply(P.W2[e], P.mW2[e], P.vW2[e], s, a);
+  }
+  for (int r = t; r < H2; r += 256) {
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) s += da2_ws[b * H2 + r];
+    if (mode == 1) P.gb2[r] = s;
+    else adam_apply(P.b2[r], P.mb2[r], P.vb2[r], s, a);
+  }
+  for (int e = t; e < H1 * Pin; e += 256) {
+    const int q = e / Pin, c = e % Pin;
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) s = fmaf(da1_ws[b * H1 + q], phat[b * Pin + c], s);
+    if (mode == 1) P.gW1[e] = s;
+    else adam_apply(P.W1[e], P.mW1[e], P.vW1[e], s, a);
+  }
+  for (int q = t; q < H1; q += 256) {
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) s += da1_ws[b * H1 + q];
+    if (mode == 1) P.gb1[q] = s;
+    else adam_apply(P.b1[q], P.mb1[q], P.vb1[q], s, a);
+  }
+}
+
+// ---- guess assembly and projection -----------------------------------------------------------
+__global__ void k_sine_table(double* __restrict__ S, int M, int Ks) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * Ks) return;
+  const int i = e / Ks, s = e % Ks;
+  const long long ph = (long long)(i + 1) * (s + 1) % (2 * (M + 1));
+  S[e] = sinpi((double)ph / (M + 1));
+}
+
+// U[t][i] = sum_s Y[t][s] S[i][s], Y[t][s] = sum_k cs[k] g[k][t][s]; one block per t.
+__global__ void __launch_bounds__(256) k_guess_assemble(const float* __restrict__ g,
+                                                        const double* __restrict__ cs, int nsrc,
+                                                        int Nt, int Ks, int M,
+                                                        const double* __restrict__ S,
+                                                        double* __restrict__ U) {
+  __shared__ double Y[256];
+  const int t = blockIdx.x;
+  for (int s = threadIdx.x; s < Ks; s += 256) {
+    double acc = 0.0;
+    for (int k = 0; k < nsrc; ++k) acc += cs[k] * (double)g[((size_t)k * Nt + t) * Ks + s];
+    Y[s] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < M; i += 256) {
+    double acc = 0.0;
+    for (int s = 0; s < Ks; ++s) acc = fma(Y[s], S[(size_t)i * Ks + s], acc);
+    U[(size_t)t * M + i] = acc;
+  }
+}
+
+// Y[t][s] = factor (2/(M+1)) sum_i U[t][i] S[i][s]; one block per t, one thread per s.
+__global__ void __launch_bounds__(256) k_project_sine(const double* __restrict__ U, int M, int Ks,
+                                                      const double* __restrict__ S, double factor,
+                                                      float* __restrict__ Y) {
+  const int t = blockIdx.x, s = threadIdx.x;
+  if (s >= Ks) return;
+  const double* row = U + (size_t)t * M;
+  double acc = 0.0;
+  for (int i = 0; i < M; ++i) acc = fma(row[i], S[(size_t)i * Ks + s], acc);
+  Y[(size_t)t * Ks + s] = (float)(acc * factor * 2.0 / (M + 1));
+}
+
+}  // namespace rfde
+
+using namespace rfde;
+
+extern "C" {
+
+static bool mlp_ok(const rfde_mlp* m, int B) {
+  return m && B >= 1 && B <= 64 && m->Pin >= 1 && m->Pin <= 64 && m->H1 >= 1 && m->H1 <= 256 &&
+         m->H2 >= 16 && m->H2 <= 256 && m->H2 % 16 == 0 && m->NOUT >= 16 && m->NOUT % 16 == 0 &&
+         m->W1 && m->b1 && m->W2 && m->b2 && m->W3t && m->b3 && m->W3t_bf16 && m->mu && m->sd;
+}
+
+size_t rfde_mlp_workspace_bytes(const rfde_mlp* m, int B) {
+  if (!m) return 0;
+  const size_t nchunk = ((size_t)m->NOUT + KCH - 1) / KCH;
+  size_t b = 0;
+  b += (size_t)B * m->Pin * 4 + (size_t)B * m->H1 * 4 + (size_t)B * m->H2 * 4;  // phat, h1, h2
+  b += (size_t)B * m->H2 * 2;                                                  // h2 bf16
+  b += (size_t)B * m->NOUT * 4 + (size_t)B * m->NOUT * 2;                      // dg, dg bf16
+  b += nchunk * B * m->H2 * 4 + (size_t)B * m->H2 * 4;                         // dh2 parts, dh2
+  b += (size_t)B * m->H2 * 4 + (size_t)B * m->H1 * 4;                          // da2, da1
+  b += MLP_RED * 8 + 256;                                                      // loss partials
+  return b + 64 * 16;  // alignment slack
+}
+
+struct MlpWs {
+  float *phat, *h1, *h2, *dg, *dh2part, *dh2, *da2, *da1;
+  unsigned short *h2b, *dgb;
+  double* part;
+};
+static MlpWs carve(const rfde_mlp* m, int B, void* ws) {
+  unsigned char* p = (unsigned char*)ws;
+  auto take = [&](size_t bytes) {
+    unsigned char* r = p;
+    p += (bytes + 63) & ~(size_t)63;
+    return (void*)r;
+  };
+  const size_t nchunk = ((size_t)m->NOUT + KCH - 1) / KCH;
+  MlpWs w;
+  w.phat = (float*)take((size_t)B * m->Pin * 4);
+  w.h1 = (float*)take((size_t)B * m->H1 * 4);
+  w.h2 = (float*)take((size_t)B * m->H2 * 4);
+  w.h2b = (unsigned short*)take((size_t)B * m->H2 * 2);
+  w.dg = (float*)take((size_t)B * m->NOUT * 4);
+  w.dgb = (unsigned short*)take((size_t)B * m->NOUT * 2);
+  w.dh2part = (float*)take(nchunk * B * m->H2 * 4);
+  w.dh2 = (float*)take((size_t)B * m->H2 * 4);
+  w.da2 = (float*)take((size_t)B * m->H2 * 4);
+  w.da1 = (float*)take((size_t)B * m->H1 * 4);
+  w.part = (double*)take(MLP_RED * 8);
+  return w;
+}
+
+static int mlp_forward_impl(const rfde_mlp* m, const float* feats, int B, float* g, MlpWs& w,
+                            hipStream_t st) {
+  k_mlp_hidden<<<B, 256, 0, st>>>(feats, m->mu, m->sd, m->W1, m->b1, m->W2, m->b2, m->Pin, m->H1,
+                                  m->H2, w.phat, w.h1, w.h2, w.h2b);
+  RFDE_HIP(hipGetLastError());
+  const int blocks = (m->NOUT / 16 + 3) / 4;
+  const int RB = (B + 15) / 16;
+  switch (RB) {
+    case 1: k_mlp_out<1><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g); break;
+    case 2: k_mlp_out<2><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g); break;
+    case 3: k_mlp_out<3><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g); break;
+    default: k_mlp_out<4><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g); break;
+  }
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+int rfde_mlp_forward(const rfde_mlp* m, const float* feats, int B, float* g, void* ws,
+                     void* stream) {
+  if (!mlp_ok(m, B) || !feats || !g || !ws) return RFDE_EINVAL;
+  MlpWs w = carve(m, B, ws);
+  return mlp_forward_impl(m, feats, B, g, w, (hipStream_t)stream);
+}
+
+// forward + loss + backward; mode 0: Adam step, mode 1: gradients into grads (flat, parameter
+// order W1, b1, W2, b2, W3t, b3).
+static int mlp_backward(const rfde_mlp* m, const float* feats, const float* y, int B, float* g,
+                        float lr, int t, float* loss, int mode, float* grads, void* ws,
+                        hipStream_t st) {
+  MlpWs w = carve(m, B, ws);
+  {
+    const int rc = mlp_forward_impl(m, feats, B, g, w, st);
+    if (rc != RFDE_OK) return rc;
+  }
+  const size_t n = (size_t)B * m->NOUT;
+  k_mlp_loss<<<MLP_RED, 256, 0, st>>>(g, y, n, w.dg, w.dgb, w.part);
+  RFDE_HIP(hipGetLastError());
+  k_mlp_loss_final<<<1, 256, 0, st>>>(w.part, n, loss);
+  RFDE_HIP(hipGetLastError());
+  const int nchunk = (m->NOUT + KCH - 1) / KCH;
+  const int RB = (B + 15) / 16;
+  switch (RB) {
+    case 1: k_mlp_dh2<1><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part); break;
+    case 2: k_mlp_dh2<2><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part); break;
+    case 3: k_mlp_dh2<3><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part); break;
+    default: k_mlp_dh2<4><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part); break;
+  }
+  RFDE_HIP(hipGetLastError());
+  const int BH = B * m->H2;
+  k_mlp_dh2_reduce<<<(BH + 255) / 256, 256, 0, st>>>(w.dh2part, nchunk, BH, w.dh2);
+  RFDE_HIP(hipGetLastError());
+  AdamCfg a;
+  a.lr = lr; a.b1 = 0.9f; a.b2 = 0.999f; a.eps = 1e-8f;
+  a.c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)t)));
+  a.c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)t)));
+  // parameter offsets in the flat gradient buffer
+  const size_t oW1 = 0, ob1 = oW1 + (size_t)m->H1 * m->Pin, oW2 = ob1 + m->H1,
+               ob2 = oW2 + (size_t)m->H2 * m->H1, oW3 = ob2 + m->H2,
+               ob3 = oW3 + (size_t)m->NOUT * m->H2;
+  // small layers first: their backward reads W2 before the update
+  SmallParams P;
+  P.W1 = m->W1; P.b1 = m->b1; P.W2 = m->W2; P.b2 = m->b2;
+  P.mW1 = m->mW1; P.vW1 = m->vW1; P.mb1 = m->mb1; P.vb1 = m->vb1;
+  P.mW2 = m->mW2; P.vW2 = m->vW2; P.mb2 = m->mb2; P.vb2 = m->vb2;
+  P.gW1 = grads ? grads + oW1 : nullptr; P.gb1 = grads ? grads + ob1 : nullptr;
+  P.gW2 = grads ? grads + oW2 : nullptr; P.gb2 = grads ? grads + ob2 : nullptr;
+  k_mlp_small_bwd<<<1, 256, 0, st>>>(w.phat, w.h1, w.h2, w.dh2, B, m->Pin, m->H1, m->H2, P, a,
+                                      mode, w.da2, w.da1);
+  RFDE_HIP(hipGetLastError());
+  const size_t tot = (size_t)m->NOUT * m->H2;
+  k_mlp_w3<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(
+      w.dg, w.h2, B, m->H2, m->NOUT, m->W3t, m->W3t_bf16, m->mW3, m->vW3, m->b3, m->mb3, m->vb3,
+      a, mode, grads ? grads + oW3 : nullptr, grads ? grads + ob3 : nullptr);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+int rfde_mlp_grads(const rfde_mlp* m, const float* feats, const float* y, int B, float* g,
+                   float* grads, float* loss, void* ws, void* stream) {
+  if (!mlp_ok(m, B) || !feats || !y || !g || !grads || !loss || !ws) return RFDE_EINVAL;
+  return mlp_backward(m, feats, y, B, g, 0.f, 1, loss, 1, grads, ws, (hipStream_t)stream);
+}
+
+int rfde_mlp_train_step(const rfde_mlp* m, const float* feats, const float* y, int B, float* g,
+                        float lr, int t, float* loss, void* ws, void* stream) {
+  if (!mlp_ok(m, B) || !feats || !y || !g || !loss || !ws || t < 1 || !(lr > 0.f) || !m->mW1 ||
+      !m->vW1 || !m->mb1 || !m->vb1 || !m->mW2 || !m->vW2 || !m->mb2 || !m->vb2 || !m->mW3 ||
+      !m->vW3 || !m->mb3 || !m->vb3)
+    return RFDE_EINVAL;
+  return mlp_backward(m, feats, y, B, g, lr, t, loss, 0, nullptr, ws, (hipStream_t)stream);
+}
+
+__global__ void k_f32_to_bf16(const float* __restrict__ a, unsigned short* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    b[i] = f2bf(a[i]);
+}
+
+int rfde_f32_to_bf16(size_t n, const float* src, unsigned short* dst, void* stream) {
+  if (!src || !dst) return RFDE_EINVAL;
+  if (n == 0) return RFDE_OK;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 16384);
+  k_f32_to_bf16<<<blocks, 256, 0, (hipStream_t)stream>>>(src, dst, n);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+int rfde_sine_table(int M, int Ks, double* S, void* stream) {
+  if (M < 1 || Ks < 1 || Ks > 256 || !S) return RFDE_EINVAL;
+  k_sine_table<<<(M * Ks + 255) / 256, 256, 0, (hipStream_t)stream>>>(S, M, Ks);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+int rfde_guess_assemble(int nsrc, int Nt, int Ks, int M, const float* g, const double* coef_scaled,
+                        const double* S, double* U, void* stream) {
+  if (nsrc < 1 || Nt < 1 || Ks < 1 || Ks > 256 || M < 1 || !g || !coef_scaled || !S || !U)
+    return RFDE_EINVAL;
+  k_guess_assemble<<<Nt, 256, 0, (hipStream_t)stream>>>(g, coef_scaled, nsrc, Nt, Ks, M, S, U);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+int rfde_project_sine(int Nt, int M, int Ks, const double* U, const double* S, double factor,
+                      float* Y, void* stream) {
+  if (Nt < 1 || M < 1 || Ks < 1 || Ks > 256 || !U || !S || !Y) return RFDE_EINVAL;
+  k_project_sine<<<Nt, 256, 0, (hipStream_t)stream>>>(U, M, Ks, S, factor, Y);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+}  // extern "C"

@@ -447,6 +447,13 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
   RFDE_TRY(fetch(1));
   if (U_init) RFDE_TRY(add_mv_time());
   double beta = hr[0];
+  if (U_init && !(beta < bnorm)) {
+    // the guess does not reduce the residual: fall back to the zero start
+    RFDE_HIP(hipMemsetAsync(x, 0, N * sizeof(double), st));
+    RFDE_HIP(hipMemcpyAsync(r, p.Fvec, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    RFDE_HIP(hipMemcpyAsync(p.redout, &bnorm, sizeof(double), hipMemcpyHostToDevice, st));
+    beta = bnorm;
+  }
   if (!std::isfinite(beta)) return RFDE_ENAN;
   loc.res_hist[0] = beta / bnorm;
   loc.n_hist = 1;

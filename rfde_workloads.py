@@ -144,3 +144,36 @@ def example2_source(g1, g2, k1, k2, x, y, t):
     return (-e / 3.0 * X * Y
             + k1 * e / (2.0 * np.cos(g1 * np.pi / 2.0)) * Y * _riesz_poly_part(g1, x)
             + k2 * e / (2.0 * np.cos(g2 * np.pi / 2.0)) * X * _riesz_poly_part(g2, y))
+
+
+# ---------------------------------------------------------------------------------------------
+# Learned initial guess: parameter draws and unit data components (inputs only).
+
+LEARNED = dict(name="1d_M1023_Nt512_learned", M=1023, Nt=512, T=1.0, Ks=64, nsrc=16,
+               train_points=625, train_seed=5000, heldout_seed=15000)
+
+
+def learned_param_draw(seed: int):
+    """alpha ~ U(1.1, 1.9), kappa ~ LogNormal(0, 0.5) from numpy default_rng(seed), in that order."""
+    rng = np.random.default_rng(seed)
+    return float(rng.uniform(1.1, 1.9)), float(rng.lognormal(0.0, 0.5))
+
+
+def learned_instance(seed: int, M: int, Nt: int, T: float = 1.0):
+    """A held-out instance: (alpha, kappa) as learned_param_draw, then gen1d data with the same
+    seed.  Returns alpha, kappa, u0, f, coefficient vector c = (a_1..a_8, b_1..b_8)."""
+    alpha, kappa = learned_param_draw(seed)
+    u0, f, (ak, bk) = gen1d(seed, M, Nt, T)
+    return alpha, kappa, u0, f, np.concatenate([ak, bk])
+
+
+def unit_data(k: int, M: int, Nt: int, T: float = 1.0):
+    """Unit data component k = 0..15: k < 8 -> u0 = sin((k+1) pi x), f = 0; k >= 8 ->
+    u0 = 0, f = exp(-t) sin((k-7) pi x).  The gen1d data are sum_k c_k unit_data(k)."""
+    x = grid_1d(0.0, 1.0, M)
+    t = time_levels(T, Nt)
+    mode = (k % N_MODES) + 1
+    s = np.sin(mode * np.pi * x)
+    if k < N_MODES:
+        return s.copy(), np.zeros((Nt, M))
+    return np.zeros(M), np.exp(-t)[:, None] * s[None, :]

@@ -36,12 +36,20 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="1d_M4095_Nt1024",
                     choices=["1d_M4095_Nt1024", "1d_M63_Nt64"])
-    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--forms", default="fp64,fp32,learned,batched")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--alphas", default="")
     ap.add_argument("--pinv-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels-only", action="store_true")
     ap.add_argument("--precond-bits", type=int, default=64, choices=[64, 32])
+    ap.add_argument("--learned-train", type=int, default=625)
+    ap.add_argument("--learned-epochs", type=int, default=600)
+    ap.add_argument("--learned-heldout", type=int, default=64)
+    ap.add_argument("--learned-ks", type=int, default=64)
+    ap.add_argument("--learned-h1", type=int, default=128)
+    ap.add_argument("--learned-h2", type=int, default=256)
+    ap.add_argument("--learned-lr", type=float, default=1e-3)
     return ap.parse_args()
 
 
@@ -156,6 +164,136 @@ def measure_form(bits, args, W, alphas, inputs, dev):
                          "traffic": None})
 
 
+def measure_learned(args, dev):
+    """The learned-guess form at its own workload (M = 1023, N_t = 512): train on solver-made
+    data, then time (setup + guess + solve) against (setup + zero-guess solve) on held-out
+    instances.  Training cost is reported separately (a one-time cost)."""
+    import torch
+
+    from paper_2003_07020_amd.learned import LearnedGuess
+    from paper_2003_07020_amd.rfde import Plan
+    import rfde_workloads as wl
+    LW = wl.LEARNED
+    M, Nt, T = LW["M"], LW["Nt"], LW["T"]
+    Ks = args.learned_ks
+    units = [wl.unit_data(j, M, Nt, T) for j in range(LW["nsrc"])]
+    t0 = time.perf_counter()
+    lg = LearnedGuess(M, Nt, units, T=T, Ks=Ks, H1=args.learned_h1, H2=args.learned_h2, seed=0)
+    draws = [wl.learned_param_draw(LW["train_seed"] + i) for i in range(args.learned_train)]
+    feats, Y, nsolve = lg.generate(draws)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = lg.train(feats, Y, epochs=args.learned_epochs, batch=32, lr0=args.learned_lr, lr1=2e-5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del Y
+    rec = []
+    for i in range(args.learned_heldout):
+        seed = LW["heldout_seed"] + i
+        alpha, kappa, u0, f, c = wl.learned_instance(seed, M, Nt, T)
+        u0d, fd = torch.from_numpy(u0).to(dev), torch.from_numpy(f.ravel()).to(dev)
+        for use in (False, True):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            p = Plan.create_1d(alpha, kappa, 0.0, 1.0, M, Nt, T, tol=1e-8)
+            Ug = lg.guess(alpha, kappa, c) if use else None
+            U, st, _ = p.solve(u0d, fd, U_init=Ug)
+            tb = time.perf_counter()
+            r = dict(seed=seed, guess=use, ms=(tb - ta) * 1e3, iters=st.iters,
+                     true_rel_res=st.true_rel_res)
+            if use:
+                r["guess_rel_err"] = float(torch.linalg.norm(Ug - U) / torch.linalg.norm(U))
+            rec.append(r)
+            p.destroy()
+    z = [r for r in rec if not r["guess"]][1:]   # first zero-guess solve includes warm-up
+    g = [r for r in rec if r["guess"]][1:]
+    return {"workload": LW["name"], "M": M, "Nt": Nt, "Ks": Ks, "H1": args.learned_h1,
+            "H2": args.learned_h2, "epochs": args.learned_epochs,
+            "train_draws": args.learned_train, "train_solves": nsolve,
+            "train_gen_s": round(t_gen, 2), "train_s": round(t_train, 2),
+            "loss_history": [float(f"{h:.4g}") for h in hist],
+            "heldout": len(z),
+            "zero_guess_ms": round(float(np.mean([r["ms"] for r in z])), 3),
+            "learned_guess_ms": round(float(np.mean([r["ms"] for r in g])), 3),
+            "zero_guess_iters": round(float(np.mean([r["iters"] for r in z])), 3),
+            "learned_guess_iters": round(float(np.mean([r["iters"] for r in g])), 3),
+            "guess_rel_err_median": float(np.median([r["guess_rel_err"] for r in g])),
+            "speedup": round(float(np.mean([r["ms"] for r in z]) / np.mean([r["ms"] for r in g])), 3)}
+
+
+def measure_batched(args, dev):
+    """The batched form on the uneven workload (64 instances, M ~ U{511..4095},
+    N_t ~ U{128..1024}, FP32 preconditioner, tol 1e-8): one rfde_batch_solve call (setup,
+    factors, lockstep FGMRES, in memory waves) against the same instances solved one by one
+    with the FP32 and with the plain FP64 single-instance solver."""
+    import torch
+
+    from paper_2003_07020_amd.rfde import Batch, Plan
+    import rfde_workloads as wl
+    inst = wl.batched_1d_instances(args.batch_count)
+    u0s, fs, host = [], [], []
+    for d in inst:
+        u0, f, _ = wl.gen1d(d["seed"], d["M"], d["Nt"])
+        host.append((u0, f))
+        u0s.append(torch.from_numpy(u0).to(dev))
+        fs.append(torch.from_numpy(f.ravel()).to(dev))
+    outs = [torch.empty_like(f) for f in fs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = Batch(inst, tol=1e-8, precond_bits=32)
+    _, stats, _ = b.solve(u0s, fs, outs)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3
+    info = b.info
+    b.destroy()
+    flops = sum((d["Nt"] // 2 + 1) * (4.0 / 3.0) * float(d["M"]) ** 3 for d in inst)
+
+    def one_by_one(bits):
+        U = torch.empty(max(d["M"] * d["Nt"] for d in inst), dtype=torch.float64, device=dev)
+        iters = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for d, u0, f in zip(inst, u0s, fs):
+            p = Plan.create_1d(d["alpha"], d["kappa"], 0.0, 1.0, d["M"], d["Nt"], d["T"],
+                               tol=1e-8, precond_bits=bits)
+            _, st, _ = p.solve(u0, f, out=U[: d["M"] * d["Nt"]])
+            iters.append(st.iters)
+            p.destroy()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, iters
+
+    ms32, it32 = one_by_one(32)
+    ms64, it64 = one_by_one(64)
+    # the two smallest instances against the oracle's march
+    from oracle import allatonce as aa
+    errs = []
+    for i in sorted(range(len(inst)), key=lambda i: inst[i]["M"] * inst[i]["Nt"])[:2]:
+        d = inst[i]
+        u0, f = host[i]
+        h, tau = aa.mesh(0.0, 1.0, d["M"], d["T"], d["Nt"])
+        ref = aa.bdf2_march(u0, f, aa.jacobian_A(d["alpha"], d["kappa"], h, d["M"]), tau)
+        Ug = outs[i].cpu().numpy().reshape(d["Nt"], d["M"])
+        errs.append(float(np.max(np.abs(Ug - ref)) / np.max(np.abs(ref))))
+    return {"workload": f"1d_batch{len(inst)}_uneven", "instances": len(inst),
+            "waves": info["waves"], "max_wave": info["max_wave"],
+            "device_GB_largest_wave": round(info["device_bytes_max"] / 1e9, 2),
+            "ms_total": round(ms_batch, 1), "ms_setup": round(info["ms_setup"], 1),
+            "ms_factor": round(info["ms_factor"], 1), "ms_solve": round(info["ms_solve"], 1),
+            "factor_TFLOPs": round(flops / (info["ms_factor"] * 1e-3) / 1e12, 2),
+            "graph_launches": info["graph_launches"],
+            "iters_mean": round(float(np.mean([s.iters for s in stats])), 2),
+            "iters_max": int(max(s.iters for s in stats)),
+            "all_converged": bool(all(s.converged for s in stats)),
+            "max_true_rel_res": float(max(s.true_rel_res for s in stats)),
+            "rel_err_vs_oracle_two_smallest": errs,
+            "one_by_one_fp32_ms": round(ms32, 1), "one_by_one_fp64_ms": round(ms64, 1),
+            "iters_mean_one_by_one_fp32": round(float(np.mean(it32)), 2),
+            "iters_mean_one_by_one_fp64": round(float(np.mean(it64)), 2),
+            "speedup_vs_one_by_one_fp32": round(ms32 / ms_batch, 3),
+            "speedup_vs_one_by_one_fp64": round(ms64 / ms_batch, 3)}
+
+
 def kernels_only(W, dev):
     import torch
 
@@ -202,6 +340,9 @@ def main():
         u0, f, _ = gen1d(W["seed"] + i, M, Nt, T)
         inputs.append((a, torch.from_numpy(u0).to(dev), torch.from_numpy(f.ravel()).to(dev), u0, f))
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    learned = measure_learned(args, dev) if "learned" in forms else None
+    batched = measure_batched(args, dev) if "batched" in forms else None
+    forms = [f for f in forms if f not in ("learned", "batched")]
     results = {f: measure_form(32 if f == "fp32" else 64, args, W, alphas, inputs, dev)
                for f in forms}
     base = results[forms[0]]
@@ -248,6 +389,10 @@ def main():
         "roofline_step_b": base["roofline_step_b"],
         "forms": forms_out,
     }
+    if learned is not None:
+        out["forms"]["learned"] = learned
+    if batched is not None:
+        out["forms"]["batched"] = batched
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

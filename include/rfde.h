@@ -120,8 +120,10 @@ int rfde_gk(double alpha, int n, double* g, void* hip_stream);
  * T_x (length L = 2^ceil(log2(2M-1)), scaled by tau kappa / h^alpha), eps, s_j = eps^{j/N_t},
  * lambda_n (eq. (3.3)) and, for RFDE_SPATIAL_EXACT, the LDL^T factors of the floor(N_t/2)+1
  * shifted blocks lambda_n I + (tau kappa / h^alpha) T_x.  Synchronous.
- *   alpha in (1, 2], kappa > 0, b > a, 1 <= M <= 4096, 2 <= N_t <= 8192 with N_t a power of
- *   two, T > 0; opts may be NULL (defaults).  RFDE_SPATIAL_TAU needs M + 1 a power of two.
+ *   alpha in (1, 2], kappa > 0, b > a, 1 <= M <= 4096, T > 0, and N_t >= 2 either a power of
+ *   two up to 8192 or any other count up to 4096 (its time DFTs then use Bluestein's chirp-z
+ *   form with a power-of-two length >= 2 N_t - 1); opts may be NULL (defaults).
+ *   RFDE_SPATIAL_TAU needs M + 1 a power of two.
  * Memory: the factors take n_freq * T(T+1)/2 * 4096 complex entries (T = ceil(M/64); 16 bytes
  * each in FP64, 8 in FP32): 69.9 GB for M = 4095, N_t = 1024 in FP64.
  * Errors: EINVAL on any range violation; EUNSUPPORTED for TAU with M + 1 not a power of two;
@@ -199,6 +201,102 @@ int rfde_apply_Pinv(rfde_plan plan, const double* v, double* z);
 int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* U_init,
                double* U, double tol, rfde_stats* stats);
 
+
+/* ------------------------------------------------------------------------------------------
+ * Launch-shape tuning (not in the paper).  Every variant computes the same result; only the
+ * work split differs.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int time_variant;      /* time FFTs: NB >> v transforms per workgroup, v in 0..2            */
+  int matvec_variant;    /* 0 default; 1 other workgroup size; 2 largest FFT radix 8          */
+  int trsv_grid_cap;     /* 0 one workgroup per block; else persistent workgroups             */
+  int from_cache;        /* bit 0 time, bit 1 matvec, bit 2 trsv: taken from the cache        */
+  double ms_time[3];     /* timed forward + inverse time FFT per variant (0 when cached)      */
+  double ms_matvec[3];   /* timed matvec per variant                                           */
+  int trsv_caps[5];      /* candidate caps                                                      */
+  double ms_trsv[5];     /* timed triangular solves per cap (-1: not applicable)               */
+} rfde_tune_report;
+
+/*
+ * Time every variant of the plan's per-iteration kernels on its own buffers and keep the
+ * fastest for later calls on this plan.  Choices are cached per shape in the process and, if
+ * the environment variable RFDE_TUNE_CACHE names a file, appended to it and read back by later
+ * processes.  Synchronous; overwrites the plan's work buffers (not its factors).  report may be
+ * NULL.  Errors: EINVAL (NULL plan), EHIP.
+ */
+int rfde_plan_autotune(rfde_plan plan, rfde_tune_report* report);
+
+/* Set the variants directly (time_variant 0..2, matvec_variant 0..2, trsv_grid_cap >= 0). */
+int rfde_plan_set_variants(rfde_plan plan, int time_variant, int matvec_variant,
+                           int trsv_grid_cap);
+
+/* ------------------------------------------------------------------------------------------
+ * Batched solves (not in the paper; a growth direction of this library).  Many independent 1D
+ * problems of Section 2 with their own alpha, kappa, domain, M, N_t and T, each solved exactly
+ * as rfde_solve does (its own epsilon-circulant preconditioner of Section 3, exact shifted
+ * solves, FGMRES(m) to the true relative residual), but with every step launched for all
+ * instances at once: the factorisations of all blocks of all instances share one launch per
+ * tile column; Arnoldi step j of all instances is one HIP graph, replayed across restart
+ * cycles; one host synchronisation per Arnoldi step for the whole set.
+ * ------------------------------------------------------------------------------------------ */
+
+/* One problem: u_t = kappa R^alpha u + f on (a, b) x (0, T], M interior points, N_t steps. */
+typedef struct {
+  double alpha, kappa, a, b, T;
+  int M, Nt;
+} rfde_instance;
+
+typedef struct rfde_batch_* rfde_batch;
+
+typedef struct {
+  int count;              /* instances                                                        */
+  int waves;              /* memory waves (groups whose factors fit the budget together)      */
+  int max_wave;           /* most instances in one wave (<= 64)                               */
+  size_t budget_bytes;    /* device-memory budget used to form the waves                      */
+  size_t wave_bytes_max;  /* estimated device bytes of the largest wave                        */
+  size_t instance_bytes_max; /* estimated device bytes of the largest instance                 */
+  size_t device_bytes_max;/* device bytes actually held by the largest wave of the last solve */
+  double ms_setup;        /* last rfde_batch_solve, summed over waves: plan setup + factors   */
+  double ms_factor;       /* ... device time of the factorisation launches (HIP events)       */
+  double ms_solve;        /* ... right-hand sides + FGMRES + true residuals (wall)            */
+  int graph_launches;     /* ... Arnoldi-step graphs launched                                 */
+} rfde_batch_info;
+
+/*
+ * Create a batch of `count` instances.  Every instance is validated as rfde_plan_create_1d
+ * validates its arguments (EINVAL, EUNSUPPORTED); opts apply to all of them (spatial must be
+ * RFDE_SPATIAL_EXACT, else EUNSUPPORTED).  mem_budget = device bytes the batch may hold at
+ * once (0: 95% of the free memory); instances are packed, largest first, into waves of at most
+ * 64 instances that fit it; ENOMEM if one instance alone does not fit.  No device memory is
+ * held between calls.  hip_stream: the caller's stream (rfde_batch_solve synchronises with it
+ * on entry and runs on a stream of its own, which graph capture needs).
+ */
+int rfde_batch_create(rfde_batch* batch, int count, const rfde_instance* inst,
+                      const rfde_opts* opts, size_t mem_budget, void* hip_stream);
+
+/*
+ * Solve every instance.  u0[i] ([M_i] FP64), f[i] ([N_t,i][M_i] FP64, levels 1..N_t) and U[i]
+ * ([N_t,i][M_i] FP64) are device pointers (host arrays of `count` pointers).  stats may be NULL
+ * (else `count` entries; ms_setup / ms_solve are those of the instance's wave).  Synchronous.
+ * Returns OK when every instance converged, ENOTCONV if some stopped at maxit (their U holds
+ * the last iterate), ENAN if some met a non-finite value, EINVAL/ENOMEM/EHIP otherwise.
+ */
+int rfde_batch_solve(rfde_batch batch, const double* const* u0, const double* const* f,
+                     double* const* U, rfde_stats* stats);
+
+/* Grid caps of the batched factor and triangular-solve launches: 0 = one workgroup per work
+ * item; c > 0 = at most c persistent workgroups looping over the items. */
+int rfde_batch_set_grid_caps(rfde_batch batch, int factor_cap, int trsv_cap);
+
+/* Tune the launch shapes of every instance's time FFTs (what bit 0) and matvec (bit 1) as
+ * rfde_plan_autotune does, before its wave is solved (0: built-in shapes, the default). */
+int rfde_batch_set_autotune(rfde_batch batch, int what);
+
+/* Wave index of instance `index` (>= 0), or EINVAL. */
+int rfde_batch_wave_of(rfde_batch batch, int index);
+
+int rfde_batch_get_info(rfde_batch batch, rfde_batch_info* info);
+int rfde_batch_destroy(rfde_batch batch);
 
 /* ------------------------------------------------------------------------------------------
  * Learned initial guess (not in the paper; a growth direction of this library).

@@ -44,6 +44,27 @@ class PlanInfo(C.Structure):
                 ("ms_factor", C.c_double)]
 
 
+class Instance(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("kappa", C.c_double), ("a", C.c_double),
+                ("b", C.c_double), ("T", C.c_double), ("M", C.c_int), ("Nt", C.c_int)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("count", C.c_int), ("waves", C.c_int), ("max_wave", C.c_int),
+                ("budget_bytes", C.c_size_t), ("wave_bytes_max", C.c_size_t),
+                ("instance_bytes_max", C.c_size_t),
+                ("device_bytes_max", C.c_size_t), ("ms_setup", C.c_double),
+                ("ms_factor", C.c_double), ("ms_solve", C.c_double),
+                ("graph_launches", C.c_int)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("time_variant", C.c_int), ("matvec_variant", C.c_int),
+                ("trsv_grid_cap", C.c_int), ("from_cache", C.c_int),
+                ("ms_time", C.c_double * 3), ("ms_matvec", C.c_double * 3),
+                ("trsv_caps", C.c_int * 5), ("ms_trsv", C.c_double * 5)]
+
+
 class RfdeError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -81,10 +102,22 @@ def lib() -> C.CDLL:
     L.rfde_pinv_step_c.argtypes = [vp, vp, vp]
     L.rfde_apply_Pinv.argtypes = [vp, vp, vp]
     L.rfde_solve.argtypes = [vp, vp, vp, vp, vp, d, C.POINTER(Stats)]
+    L.rfde_plan_autotune.argtypes = [vp, C.POINTER(TuneReport)]
+    L.rfde_plan_set_variants.argtypes = [vp, i, i, i]
+    L.rfde_batch_create.argtypes = [C.POINTER(vp), i, C.POINTER(Instance), C.POINTER(Opts),
+                                    C.c_size_t, vp]
+    L.rfde_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                   C.POINTER(Stats)]
+    L.rfde_batch_set_grid_caps.argtypes = [vp, i, i]
+    L.rfde_batch_set_autotune.argtypes = [vp, i]
+    L.rfde_batch_wave_of.argtypes = [vp, i]
+    L.rfde_batch_get_info.argtypes = [vp, C.POINTER(BatchInfo)]
+    L.rfde_batch_destroy.argtypes = [vp]
     for name in ("rfde_gk", "rfde_plan_create_1d", "rfde_plan_create_2d", "rfde_plan_destroy",
                  "rfde_plan_get_info", "rfde_plan_export", "rfde_build_rhs", "rfde_apply_A",
                  "rfde_pinv_step_a", "rfde_pinv_step_b", "rfde_pinv_step_c", "rfde_apply_Pinv",
-                 "rfde_solve"):
+                 "rfde_solve", "rfde_plan_autotune", "rfde_plan_set_variants", "rfde_batch_create", "rfde_batch_solve", "rfde_batch_set_grid_caps", "rfde_batch_set_autotune",
+                 "rfde_batch_wave_of", "rfde_batch_get_info", "rfde_batch_destroy"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -106,9 +106,10 @@ template <int R, int SIGN, typename C> __device__ __forceinline__ void dft_r(C* 
   else dft16<SIGN>(v);
 }
 
-// Radix chosen for the pass that follows a sub-length Ns of a length-N transform.
-__host__ __device__ constexpr int pass_radix(int N, int Ns) {
-  return (N / Ns) >= 16 ? 16 : (N / Ns);
+// Radix chosen for the pass that follows a sub-length Ns of a length-N transform (largest
+// radix MAXR, 16 or 8; the last pass takes what remains).
+__host__ __device__ constexpr int pass_radix(int N, int Ns, int MAXR = 16) {
+  return (N / Ns) >= MAXR ? MAXR : (N / Ns);
 }
 
 // Placeholder functors for passes that stay inside LDS.
@@ -182,26 +183,25 @@ __device__ __forceinline__ void stockham_pass_io(C* buf, const C* __restrict__ t
 }
 
 template <int N, int Ns, int SIGN, int NT, int NB, int LDN, bool BFAST, bool FIRST_EXT,
-          bool LAST_EXT, typename C, typename Load, typename Store>
+          bool LAST_EXT, int MAXR, typename C, typename Load, typename Store>
 __device__ __forceinline__ void fft_passes(C* buf, const C* __restrict__ tw, Load& load,
                                            Store& store) {
-  constexpr int R = pass_radix(N, Ns);
+  constexpr int R = pass_radix(N, Ns, MAXR);
   constexpr bool last = (Ns * R >= N);
   stockham_pass_io<N, R, Ns, SIGN, NT, NB, LDN, BFAST, FIRST_EXT && Ns == 1, LAST_EXT && last>(
       buf, tw, load, store);
   if constexpr (!last) {
-    fft_passes<N, Ns * R, SIGN, NT, NB, LDN, BFAST, FIRST_EXT, LAST_EXT>(buf, tw, load, store);
-  } else if constexpr (!LAST_EXT) {
-    // the final pass wrote buf and synchronised
+    fft_passes<N, Ns * R, SIGN, NT, NB, LDN, BFAST, FIRST_EXT, LAST_EXT, MAXR>(buf, tw, load,
+                                                                               store);
   }
 }
 
 // Length-N transform of NB sequences, first inputs from load(f, idx) (or buf), last outputs to
 // store(f, idx, value) (or buf, natural order).  N must be a power of two >= 2.
 template <int N, int SIGN, int NT, int NB, int LDN, bool BFAST, bool FIRST_EXT, bool LAST_EXT,
-          typename C, typename Load, typename Store>
+          int MAXR = 16, typename C, typename Load, typename Store>
 __device__ __forceinline__ void fft_io(C* buf, const C* __restrict__ tw, Load& load, Store& store) {
-  fft_passes<N, 1, SIGN, NT, NB, LDN, BFAST, FIRST_EXT, LAST_EXT>(buf, tw, load, store);
+  fft_passes<N, 1, SIGN, NT, NB, LDN, BFAST, FIRST_EXT, LAST_EXT, MAXR>(buf, tw, load, store);
 }
 
 // Full length-N transform of NB batched sequences held in LDS (natural order in and out,
@@ -210,7 +210,7 @@ template <int N, int SIGN, int NT, int NB, typename C>
 __device__ __forceinline__ void fft_lds(C* buf, const C* __restrict__ tw) {
   NoLoad nl;
   NoStore ns;
-  fft_passes<N, 1, SIGN, NT, NB, N, false, false, false>(buf, tw, nl, ns);
+  fft_passes<N, 1, SIGN, NT, NB, N, false, false, false, 16>(buf, tw, nl, ns);
 }
 
 }  // namespace rfde

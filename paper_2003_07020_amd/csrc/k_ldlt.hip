@@ -24,6 +24,8 @@
 //                 diagonal launches, which have only one workgroup per block, do no GEMM work.
 // B_ij is generated from g, coef and lambda_n in the accumulator initialisation, so the
 // assembled matrices are never stored.  Complex products use four real MFMAs each.
+#include <algorithm>
+
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"
 
@@ -69,6 +71,17 @@ __device__ __forceinline__ double2 shifted_entry(const double* __restrict__ g, d
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   const int x = b & 7, q = nb >> 3, r = nb & 7;
   return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Family slot k of an item map holding `item` (binary search over the start offsets).
+__device__ __forceinline__ int find_slot(const ItemMap& m, int item) {
+  int lo = 0, hi = m.cnt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (m.start[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // Accumulators of one wave: 2x2 blocks of 16x16, real and imaginary parts.
@@ -257,19 +270,24 @@ __device__ __forceinline__ void acc_to_lds(const WaveAcc<C>& acc, C* __restrict_
 // column c of L^{-1} transposed, S[r*LD + c] = Linv[r][c] for r > c.  The stored tile (entry
 // (rr, cc) at cc*64 + rr) is then exactly S read transposed: Linv below the diagonal, d on it,
 // L transposed above it.
-template <typename C>
-__global__ void __launch_bounds__(256) k_ldlt_diag(C* __restrict__ factors, size_t sys_elems,
-                                                   int j, const double* __restrict__ g,
-                                                   double coef,
-                                                   const double2* __restrict__ lambda, int M) {
+// Items: the blocks n of every family with more than j tile columns.
+template <typename C, bool P>
+__global__ void __launch_bounds__(256) k_ldlt_diag(const BlockSet* __restrict__ set, ItemMap map,
+                                                   int j) {
   using R = typename mma<C>::R;
   __shared__ C S[TILE * LDSLD];
-  const int n = blockIdx.x;
-  C* fac = factors + (size_t)n * sys_elems;
+  auto body = [&](int item) {
+  const int slot = find_slot(map, item);
+  const int fm = map.fam[slot];
+  const int n = item - map.start[slot];
+  const int M = set->M[fm];
+  const double* __restrict__ g = set->g[fm];
+  const double coef = set->coef[fm];
+  C* fac = (C*)set->fac[fm] + (size_t)n * lower_tiles(set->T[fm]) * TILE_ELEMS;
   C* Djj = fac + tile_index(j, j) * TILE_ELEMS;
   const int t = threadIdx.x;
   if (j == 0) {
-    const double2 lam = lambda[n];
+    const double2 lam = set->lambda[fm][n];
     for (int e = t; e < TILE_ELEMS; e += 256) {
       const int c = e >> 6, r = e & 63;
       const double2 b = shifted_entry(g, coef, lam, M, r, c);
@@ -309,30 +327,45 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(C* __restrict__ factors, size
   }
   __syncthreads();
   for (int e = t; e < TILE_ELEMS; e += 256) Djj[e] = S[(e & 63) * LDSLD + (e >> 6)];
+  __syncthreads();  // S is reused by the next item
+  };
+  if constexpr (P) {
+    for (int item = blockIdx.x; item < map.start[map.cnt]; item += gridDim.x) body(item);
+  } else {
+    body(blockIdx.x);
+  }
 }
 
-template <typename C>
-__global__ void __launch_bounds__(256) k_ldlt_panel(C* __restrict__ factors, size_t sys_elems,
-                                                    int j, int T, const double* __restrict__ g,
-                                                    double coef,
-                                                    const double2* __restrict__ lambda, int M) {
+// Items: (block n, tile row i > j) of every family with more than j + 1 tile columns, i
+// fastest.  Each round of gridDim.x items is dealt through xcd_remap so that every XCD takes a
+// contiguous range (the tiles of one block share their row-j operands in that XCD's L2).
+template <typename C, bool P>
+__global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__ set, ItemMap map,
+                                                    int j) {
   using R = typename mma<C>::R;
   // LDS: operand staging during the K loop, then the 64x64 tile S for the epilogue
   constexpr size_t SB = sizeof(StageBuf<C>), ST = sizeof(C) * TILE * LDSLD;
   __shared__ __align__(16) unsigned char smem[SB > ST ? SB : ST];
   StageBuf<C>& sb = *reinterpret_cast<StageBuf<C>*>(smem);
   C* S = reinterpret_cast<C*>(smem);
+  auto body = [&](int item) {
+  const int slot = find_slot(map, item);
+  const int fm = map.fam[slot];
+  const int T = set->T[fm], M = set->M[fm];
+  const double* __restrict__ g = set->g[fm];
+  const double coef = set->coef[fm];
   const int per = T - 1 - j;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int lb = item - map.start[slot];
   const int n = lb / per, i = j + 1 + lb % per;
-  C* fac = factors + (size_t)n * sys_elems;
+  const double2 lamn = set->lambda[fm][n];
+  C* fac = (C*)set->fac[fm] + (size_t)n * lower_tiles(T) * TILE_ELEMS;
   {
     WaveAcc<C> acc;
     if constexpr (sizeof(C) == 8) {
-      tile_update_staged<C>(acc, fac, i, j, g, coef, lambda[n], M, sb);
+      tile_update_staged<C>(acc, fac, i, j, g, coef, lamn, M, sb);
       __syncthreads();  // staging buffers are reused as S
     } else {
-      tile_update_direct<C>(acc, fac, i, j, g, coef, lambda[n], M);
+      tile_update_direct<C>(acc, fac, i, j, g, coef, lamn, M);
     }
     acc_to_lds<C>(acc, S);
   }
@@ -436,10 +469,9 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(C* __restrict__ factors, siz
   __syncthreads();  // S (L_ij) no longer needed
   C* Pii = fac + tile_index(i, i) * TILE_ELEMS;
   if (j == 0) {
-    const double2 lam = lambda[n];
     for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) {
       const int c = e >> 6, r = e & 63;
-      const double2 b = shifted_entry(g, coef, lam, M, i * TILE + r, i * TILE + c);
+      const double2 b = shifted_entry(g, coef, lamn, M, i * TILE + r, i * TILE + c);
       S[c * LDSLD + r] = cmk<C>((R)b.x, (R)b.y);
     }
   } else {
@@ -460,27 +492,75 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(C* __restrict__ factors, siz
   }
   __syncthreads();
   for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) Pii[e] = S[(e >> 6) * LDSLD + (e & 63)];
+  __syncthreads();  // smem is reused by the next item
+  };
+  const int lbr = xcd_remap(blockIdx.x, gridDim.x);
+  if constexpr (P) {
+    const int total = map.start[map.cnt];
+    for (int base = 0; base + lbr < total; base += gridDim.x) body(base + lbr);
+  } else {
+    body(lbr);
+  }
+}
+
+// Items of column j: diag -> nf per family with T > j; panel -> nf (T - 1 - j) per family.
+static ItemMap column_map(const BlockSet& hs, int j, bool panel) {
+  ItemMap m;
+  m.cnt = 0;
+  m.start[0] = 0;
+  for (int k = 0; k < hs.count; ++k) {
+    const int per = panel ? hs.T[k] - 1 - j : (hs.T[k] > j ? 1 : 0);
+    if (per <= 0) continue;
+    m.fam[m.cnt] = k;
+    m.start[m.cnt + 1] = m.start[m.cnt] + hs.nf[k] * per;
+    ++m.cnt;
+  }
+  return m;
 }
 
 template <typename C>
-static int factorize_t(Plan& p) {
-  const size_t sys = lower_tiles(p.T) * TILE_ELEMS;
-  C* fac = (C*)p.factors;
-  for (int j = 0; j < p.T; ++j) {
-    k_ldlt_diag<C><<<p.nf, 256, 0, p.stream>>>(fac, sys, j, p.g, p.coef, p.lambda, p.M);
-    RFDE_HIP(hipGetLastError());
-    if (j + 1 < p.T) {
-      const int blocks = p.nf * (p.T - 1 - j);
-      k_ldlt_panel<C><<<blocks, 256, 0, p.stream>>>(fac, sys, j, p.T, p.g, p.coef, p.lambda, p.M);
+static int factorize_t(const BlockSet& hs, const BlockSet* ds, int grid_cap, hipStream_t st) {
+  int Tmax = 0;
+  for (int k = 0; k < hs.count; ++k) Tmax = std::max(Tmax, hs.T[k]);
+  for (int j = 0; j < Tmax; ++j) {
+    const ItemMap md = column_map(hs, j, false);
+    if (md.total() > 0) {
+      if (grid_cap > 0 && grid_cap < md.total())
+        k_ldlt_diag<C, true><<<grid_cap, 256, 0, st>>>(ds, md, j);
+      else
+        k_ldlt_diag<C, false><<<md.total(), 256, 0, st>>>(ds, md, j);
+      RFDE_HIP(hipGetLastError());
+    }
+    const ItemMap mp = column_map(hs, j, true);
+    if (mp.total() > 0) {
+      if (grid_cap > 0 && grid_cap < mp.total())
+        k_ldlt_panel<C, true><<<grid_cap, 256, 0, st>>>(ds, mp, j);
+      else
+        k_ldlt_panel<C, false><<<mp.total(), 256, 0, st>>>(ds, mp, j);
       RFDE_HIP(hipGetLastError());
     }
   }
   return RFDE_OK;
 }
 
+int launch_factorize_set(const BlockSet& hs, const BlockSet* ds, int bits, int grid_cap,
+                         hipStream_t st) {
+  if (hs.count < 1 || hs.count > MAX_BATCH) return RFDE_EINVAL;
+  if (bits == 32) return factorize_t<float2>(hs, ds, grid_cap, st);
+  return factorize_t<double2>(hs, ds, grid_cap, st);
+}
+
+static BlockSet plan_set(const Plan& p) {
+  BlockSet hs{};
+  hs.count = 1;
+  hs.nf[0] = p.nf; hs.M[0] = p.M; hs.T[0] = p.T;
+  hs.fac[0] = p.factors; hs.g[0] = p.g; hs.lambda[0] = p.lambda; hs.coef[0] = p.coef;
+  hs.live[0] = p.live;
+  return hs;
+}
+
 int launch_factorize(Plan& p) {
-  if (p.opts.precond_bits == 32) return factorize_t<float2>(p);
-  return factorize_t<double2>(p);
+  return launch_factorize_set(plan_set(p), p.set, p.opts.precond_bits, 0, p.stream);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -497,16 +577,29 @@ template <typename C> __device__ __forceinline__ C wave_sum(C v) {
   return v;
 }
 
-template <typename C, int TMAX>
-__global__ void __launch_bounds__(256) k_trsv(const C* __restrict__ factors, size_t sys_elems,
-                                              const C* zin, C* zout,
-                                              int M, int T) {
+// Input/output frequency-domain arrays of the families of a trsv launch (by value).
+struct ZIO {
+  const void* in[MAX_BATCH];
+  void* out[MAX_BATCH];
+};
+
+// Items: the blocks n of every family (one workgroup each).
+template <typename C, int TMAX, bool P>
+__global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, ItemMap map,
+                                              ZIO io) {
   using R = typename mma<C>::R;
   __shared__ C xs[TMAX * TILE];
   __shared__ C red[4][TILE];
   __shared__ C tb[TILE];
-  const int n = blockIdx.x;
-  const C* fac = factors + (size_t)n * sys_elems;
+  auto body = [&](int item) {
+  const int slot = find_slot(map, item);
+  const int fm = map.fam[slot];
+  if (set->live[fm] && *set->live[fm] == 0) return;  // uniform across the workgroup
+  const int n = item - map.start[slot];
+  const int M = set->M[fm], T = set->T[fm];
+  const C* fac = (const C*)set->fac[fm] + (size_t)n * lower_tiles(T) * TILE_ELEMS;
+  const C* zin = (const C*)io.in[fm];
+  C* zout = (C*)io.out[fm];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int Mp = T * TILE;
   for (int r = t; r < Mp; r += 256) xs[r] = (r < M) ? zin[(size_t)n * M + r] : cmk<C>((R)0, (R)0);
@@ -614,24 +707,48 @@ __global__ void __launch_bounds__(256) k_trsv(const C* __restrict__ factors, siz
     __syncthreads();
   }
   for (int r = t; r < M; r += 256) zout[(size_t)n * M + r] = xs[r];
+  __syncthreads();  // xs is reused by the next item
+  };
+  if constexpr (P) {
+    for (int item = blockIdx.x; item < map.start[map.cnt]; item += gridDim.x) body(item);
+  } else {
+    body(blockIdx.x);
+  }
 }
 
-template <typename C>
-static int trsv_t(const Plan& p, const void* zin, void* zout) {
-  const size_t sys = lower_tiles(p.T) * TILE_ELEMS;
-  if (p.T <= 64) {
-    k_trsv<C, 64><<<p.nf, 256, 0, p.stream>>>((const C*)p.factors, sys, (const C*)zin, (C*)zout,
-                                              p.M, p.T);
+int launch_trsv_set(const BlockSet& hs, const BlockSet* ds, const void* const* zin,
+                    void* const* zout, int bits, int grid_cap, hipStream_t st) {
+  if (hs.count < 1 || hs.count > MAX_BATCH) return RFDE_EINVAL;
+  ItemMap m;
+  m.cnt = 0;
+  m.start[0] = 0;
+  ZIO io{};
+  for (int k = 0; k < hs.count; ++k) {
+    if (hs.T[k] > 64) return RFDE_EINVAL;
+    io.in[k] = zin[k];
+    io.out[k] = zout[k];
+    if (!zin[k] || !zout[k]) continue;  // family skipped in this launch
+    m.fam[m.cnt] = k;
+    m.start[m.cnt + 1] = m.start[m.cnt] + hs.nf[k];
+    ++m.cnt;
+  }
+  if (m.total() == 0) return RFDE_OK;
+  const bool persist = grid_cap > 0 && grid_cap < m.total();
+  const int grid = persist ? grid_cap : m.total();
+  if (bits == 32) {
+    if (persist) k_trsv<float2, 64, true><<<grid, 256, 0, st>>>(ds, m, io);
+    else k_trsv<float2, 64, false><<<grid, 256, 0, st>>>(ds, m, io);
   } else {
-    return RFDE_EINVAL;
+    if (persist) k_trsv<double2, 64, true><<<grid, 256, 0, st>>>(ds, m, io);
+    else k_trsv<double2, 64, false><<<grid, 256, 0, st>>>(ds, m, io);
   }
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
 
 int launch_trsv(const Plan& p, const void* zin, void* zout) {
-  if (p.opts.precond_bits == 32) return trsv_t<float2>(p, zin, zout);
-  return trsv_t<double2>(p, zin, zout);
+  const BlockSet hs = plan_set(p);
+  return launch_trsv_set(hs, p.set, &zin, &zout, p.opts.precond_bits, p.trsv_cap, p.stream);
 }
 
 // Export block `index` as a dense row-major Mp x Mp matrix: strict lower = L, diagonal = D.

@@ -31,12 +31,14 @@ template <int L> constexpr int mv_threads() { return L >= 2048 ? 512 : 256; }
 // Rows of length n (contiguous): one block per pair of rows (r0, r0+1) of the flattened
 // [rows][n] array; row r belongs to time level r / rows_per_level.  Writes
 // y = time stencil + (symbol-circulant product) v for both rows.
-template <int L, int NT>
+template <int L, int NT, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_matvec_rows(const double* __restrict__ v,
                                                     double* __restrict__ y,
                                                     const double* __restrict__ sym,
                                                     const double2* __restrict__ tw, int n,
-                                                    int rows, int rows_per_level, size_t S) {
+                                                    int rows, int rows_per_level, size_t S,
+                                                    const int* __restrict__ live) {
+  if (live && *live == 0) return;
   __shared__ double2 buf[L];
   const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
   const bool has1 = r1 < rows;
@@ -54,7 +56,7 @@ __global__ void __launch_bounds__(NT) k_matvec_rows(const double* __restrict__ v
     const double s = sym[idx <= L / 2 ? idx : L - idx];
     buf[idx] = make_double2(x.x * s, x.y * s);
   };
-  fft_io<L, -1, NT, 1, L, false, true, true>(buf, tw, load, store_scaled);
+  fft_io<L, -1, NT, 1, L, false, true, true, MAXR>(buf, tw, load, store_scaled);
   __syncthreads();
   const int ka = r0 / rows_per_level, kb = r1 / rows_per_level;
   auto store_out = [&](int, int idx, double2 x) {
@@ -68,7 +70,7 @@ __global__ void __launch_bounds__(NT) k_matvec_rows(const double* __restrict__ v
     }
   };
   NoLoad nl;
-  fft_io<L, +1, NT, 1, L, false, false, true>(buf, tw, nl, store_out);
+  fft_io<L, +1, NT, 1, L, false, false, true, MAXR>(buf, tw, nl, store_out);
 }
 
 // 2D, y direction: for one time level and a tile of 2*NB adjacent columns, NB complex transforms
@@ -115,20 +117,30 @@ __global__ void __launch_bounds__(NT) k_matvec_2d_y(const double* __restrict__ v
   fft_io<L, +1, NT, NB, LDN, true, false, true>(buf, tw, nl, store_out);
 }
 
-template <int L>
-static int mv1d(const Plan& p, const double* v, double* y) {
-  constexpr int NT = mv_threads<L>();
-  k_matvec_rows<L, NT><<<(p.Nt + 1) / 2, NT, 0, p.stream>>>(v, y, p.sym, p.twL, p.M, p.Nt, 1,
-                                                            (size_t)p.M);
+// Variants: 0 = default workgroup size and radix 16; 1 = the other workgroup size (256 <-> 512);
+// 2 = default size with radix-8 passes.
+template <int L, int V>
+static int mv1d_v(const Plan& p, const double* v, double* y) {
+  constexpr int NT0 = mv_threads<L>();
+  constexpr int NT = V == 1 ? (NT0 == 512 ? 256 : 512) : NT0;
+  constexpr int MAXR = V == 2 ? 8 : 16;
+  k_matvec_rows<L, NT, MAXR><<<(p.Nt + 1) / 2, NT, 0, p.stream>>>(v, y, p.sym, p.twL, p.M, p.Nt,
+                                                                  1, (size_t)p.M, p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
+}
+template <int L>
+static int mv1d(const Plan& p, const double* v, double* y) {
+  if (p.tv_matvec == 1) return mv1d_v<L, 1>(p, v, y);
+  if (p.tv_matvec == 2) return mv1d_v<L, 2>(p, v, y);
+  return mv1d_v<L, 0>(p, v, y);
 }
 template <int L>
 static int mv2dx(const Plan& p, const double* v, double* y) {
   constexpr int NT = mv_threads<L>();
   const int rows = p.Nt * p.My;
   k_matvec_rows<L, NT><<<(rows + 1) / 2, NT, 0, p.stream>>>(v, y, p.sym, p.twL, p.Mx, rows, p.My,
-                                                            (size_t)p.Mx * p.My);
+                                                            (size_t)p.Mx * p.My, nullptr);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

@@ -11,6 +11,12 @@
 // Threads take the NB transforms fastest, so every global access is a contiguous row segment
 // of TS values (128 bytes where the LDS budget allows); the first pass of step (a) reads v
 // straight from memory and the last pass of step (c) writes v straight to memory.
+//
+// Nt not a power of two: Bluestein's chirp-z form.  With w_k = exp(i pi k^2 / Nt),
+// theta^{n j} = w_n w_j conj(w_{n-j}), so X_n = w_n sum_j (x_j w_j) conj(w_{n-j}) is a linear
+// convolution of length-Nt sequences, done exactly as a cyclic one of power-of-two length
+// Lt >= 2 Nt - 1 (forward FFT, product with the precomputed DFT of the kernel, inverse FFT),
+// all in LDS.  Step (c) uses sum_n Z_n theta^{-n j} = conj(sum_n conj(Z_n) theta^{n j}).
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"
 
@@ -19,7 +25,9 @@ namespace rfde {
 template <int N, int NB, int NT, typename C>
 __global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C* __restrict__ z1,
                                                  const double* __restrict__ s,
-                                                 const C* __restrict__ tw, int S) {
+                                                 const C* __restrict__ tw, int S,
+                                                 const int* __restrict__ live) {
+  if (live && *live == 0) return;
   using R = typename cplx_traits<C>::real;
   constexpr int LDN = N + 1;
   __shared__ C buf[NB * LDN];
@@ -51,7 +59,9 @@ __global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C
 template <int N, int NB, int NT, typename C>
 __global__ void __launch_bounds__(NT) k_time_inv(const C* __restrict__ z2, double* __restrict__ v,
                                                  const double* __restrict__ s,
-                                                 const C* __restrict__ tw, int S) {
+                                                 const C* __restrict__ tw, int S,
+                                                 const int* __restrict__ live) {
+  if (live && *live == 0) return;
   using R = typename cplx_traits<C>::real;
   constexpr int LDN = N + 1;
   __shared__ C buf[NB * LDN];
@@ -79,36 +89,245 @@ __global__ void __launch_bounds__(NT) k_time_inv(const C* __restrict__ z2, doubl
   fft_io<N, -1, NT, NB, LDN, true, true, true>(buf, tw, load, store);
 }
 
+// ---- Bluestein variants (Nt not a power of two, LB = Lt) ----
+template <int LB, int NB, int NT, typename C>
+__global__ void __launch_bounds__(NT) k_time_fwd_bs(const double* __restrict__ v, C* __restrict__ z1,
+                                                    const double* __restrict__ s,
+                                                    const C* __restrict__ tw,
+                                                    const C* __restrict__ chirp,
+                                                    const C* __restrict__ bhat, int S, int Nt,
+                                                    const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  using R = typename cplx_traits<C>::real;
+  constexpr int LDN = LB + 1;
+  __shared__ C buf[NB * LDN];
+  constexpr int TS = 2 * NB;
+  const int i0 = blockIdx.x * TS;
+  auto load = [&](int f, int j) -> C {
+    if (j >= Nt) return cmk<C>((R)0, (R)0);
+    const int i = i0 + 2 * f;
+    const double* row = v + (size_t)j * S;
+    const double sj = s[j];
+    const R a = (i < S) ? (R)(sj * row[i]) : (R)0;
+    const R b = (i + 1 < S) ? (R)(sj * row[i + 1]) : (R)0;
+    return cmul(cmk<C>(a, b), chirp[j]);
+  };
+  NoLoad nl;
+  NoStore ns;
+  fft_io<LB, -1, NT, NB, LDN, true, true, false>(buf, tw, load, ns);
+  for (int e = threadIdx.x; e < NB * LB; e += NT) {
+    const int f = e % NB, k = e / NB;
+    buf[f * LDN + k] = cmul(buf[f * LDN + k], bhat[k]);
+  }
+  __syncthreads();
+  fft_io<LB, +1, NT, NB, LDN, true, false, false>(buf, tw, nl, ns);
+  const int nf = Nt / 2 + 1;
+  for (int e = threadIdx.x; e < nf * TS; e += NT) {
+    const int n = e / TS, q = e - n * TS;
+    const int i = i0 + q;
+    if (i >= S) continue;
+    const int m = n == 0 ? 0 : Nt - n;
+    const C a = cmul(chirp[n], buf[(q >> 1) * LDN + n]);
+    const C b = cconj(cmul(chirp[m], buf[(q >> 1) * LDN + m]));
+    C out;
+    if ((q & 1) == 0) out = cmk<C>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y + b.y));
+    else out = cmk<C>((R)0.5 * (a.y - b.y), (R)-0.5 * (a.x - b.x));
+    z1[(size_t)n * S + i] = out;
+  }
+}
+
+template <int LB, int NB, int NT, typename C>
+__global__ void __launch_bounds__(NT) k_time_inv_bs(const C* __restrict__ z2, double* __restrict__ v,
+                                                    const double* __restrict__ s,
+                                                    const C* __restrict__ tw,
+                                                    const C* __restrict__ chirp,
+                                                    const C* __restrict__ bhat, int S, int Nt,
+                                                    const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  using R = typename cplx_traits<C>::real;
+  constexpr int LDN = LB + 1;
+  __shared__ C buf[NB * LDN];
+  constexpr int TS = 2 * NB;
+  const int i0 = blockIdx.x * TS;
+  const int half = Nt / 2;
+  // y_n = conj(Z_n) w_n with Z_n = P_n + i Q_n rebuilt from the half spectra as in k_time_inv
+  // (only an even Nt has a self-conjugate n = Nt/2).
+  auto load = [&](int f, int n) -> C {
+    if (n >= Nt) return cmk<C>((R)0, (R)0);
+    const int ia = i0 + 2 * f, ib = ia + 1;
+    const int nn = n <= half ? n : Nt - n;
+    C P = cmk<C>((R)0, (R)0), Q = cmk<C>((R)0, (R)0);
+    if (ia < S) P = z2[(size_t)nn * S + ia];
+    if (ib < S) Q = z2[(size_t)nn * S + ib];
+    if (nn == 0 || 2 * nn == Nt) { P.y = (R)0; Q.y = (R)0; }
+    const C Z = n <= half ? cmk<C>(P.x - Q.y, P.y + Q.x) : cmk<C>(P.x + Q.y, Q.x - P.y);
+    return cmul(cconj(Z), chirp[n]);
+  };
+  // R_j = w_j conv_j = sum_n conj(Z_n) theta^{n j}; v_{2p} + i v_{2p+1} = conj(R_j) / (Nt s_j)
+  auto store = [&](int f, int j, C c) {
+    if (j >= Nt) return;
+    const C Rj = cmul(chirp[j], c);
+    const int i = i0 + 2 * f;
+    double* row = v + (size_t)j * S;
+    const double sc = 1.0 / ((double)Nt * s[j]);
+    if (i < S) row[i] = (double)Rj.x * sc;
+    if (i + 1 < S) row[i + 1] = -(double)Rj.y * sc;
+  };
+  NoStore ns;
+  fft_io<LB, -1, NT, NB, LDN, true, true, false>(buf, tw, load, ns);
+  for (int e = threadIdx.x; e < NB * LB; e += NT) {
+    const int f = e % NB, k = e / NB;
+    buf[f * LDN + k] = cmul(buf[f * LDN + k], bhat[k]);
+  }
+  __syncthreads();
+  NoLoad nl;
+  fft_io<LB, +1, NT, NB, LDN, true, false, true>(buf, tw, nl, store);
+}
+
+// w_k = exp(i pi (k^2 mod 2 Nt) / Nt) in both precisions (the integer reduction keeps the
+// angle exact before rounding).
+__global__ void k_bs_chirp(int Nt, double2* __restrict__ w, float2* __restrict__ w32) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Nt) return;
+  const long long r = ((long long)k * k) % (2LL * Nt);
+  double sn, cs;
+  sincospi((double)r / Nt, &sn, &cs);
+  w[k] = make_double2(cs, sn);
+  w32[k] = make_float2((float)cs, (float)sn);
+}
+
+// bhat = DFT_{-1}(b) / LB with the cyclic kernel b_k = conj(w_k) (k < Nt),
+// b_{LB-k} = conj(w_k) (0 < k < Nt), zero elsewhere.  One block.
+template <int LB>
+__global__ void __launch_bounds__(256) k_bs_kernel(int Nt, const double2* __restrict__ w,
+                                                   const double2* __restrict__ tw,
+                                                   double2* __restrict__ bhat,
+                                                   float2* __restrict__ bhat32) {
+  __shared__ double2 buf[LB];
+  for (int k = threadIdx.x; k < LB; k += 256) {
+    double2 b = make_double2(0.0, 0.0);
+    if (k < Nt) b = make_double2(w[k].x, -w[k].y);
+    else if (LB - k < Nt) b = make_double2(w[LB - k].x, -w[LB - k].y);
+    buf[k] = b;
+  }
+  __syncthreads();
+  fft_lds<LB, -1, 256, 1>(buf, tw);
+  for (int k = threadIdx.x; k < LB; k += 256) {
+    const double2 c = make_double2(buf[k].x / LB, buf[k].y / LB);
+    bhat[k] = c;
+    bhat32[k] = make_float2((float)c.x, (float)c.y);
+  }
+}
+
 // Transforms per block: 128-byte row segments (NB = 8 complex128 / 16 complex64 pairs) unless
-// the ~130 KB LDS budget forces fewer.
-template <int N, typename C>
+// the ~130 KB LDS budget forces fewer; variant V halves NB V times (more, smaller workgroups).
+template <int N, typename C, int V = 0>
 constexpr int time_nb() {
   constexpr int target = (int)sizeof(C) == 16 ? 8 : 16;
   constexpr int cap = 135168 / ((N + 1) * (int)sizeof(C));
-  return cap < 1 ? 1 : (cap < target ? cap : target);
+  constexpr int nb = cap < 1 ? 1 : (cap < target ? cap : target);
+  return (nb >> V) < 1 ? 1 : (nb >> V);
 }
-template <int N, typename C>
+template <int N, typename C, int V = 0>
 constexpr int time_nt() {
-  return time_nb<N, C>() * N >= 4096 ? 512 : 256;
+  return time_nb<N, C, V>() * N >= 4096 ? 512 : 256;
 }
 
-template <int N, typename C>
-static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw) {
-  constexpr int NB = time_nb<N, C>();
-  constexpr int NT = time_nt<N, C>();
+template <int N, typename C, int V>
+static int tf_fwd_v(const Plan& p, const double* v, void* z1, const C* tw) {
+  constexpr int NB = time_nb<N, C, V>();
+  constexpr int NT = time_nt<N, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_fwd<N, NB, NT, C><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S);
+  k_time_fwd<N, NB, NT, C><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S, p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
+}
+template <int N, typename C, int V>
+static int tf_inv_v(const Plan& p, const void* z2, double* v, const C* tw) {
+  constexpr int NB = time_nb<N, C, V>();
+  constexpr int NT = time_nt<N, C, V>();
+  const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
+  k_time_inv<N, NB, NT, C><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw, p.S, p.live);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+template <int N, typename C>
+static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw) {
+  if (p.tv_time == 1) return tf_fwd_v<N, C, 1>(p, v, z1, tw);
+  if (p.tv_time == 2) return tf_fwd_v<N, C, 2>(p, v, z1, tw);
+  return tf_fwd_v<N, C, 0>(p, v, z1, tw);
 }
 template <int N, typename C>
 static int tf_inv(const Plan& p, const void* z2, double* v, const C* tw) {
-  constexpr int NB = time_nb<N, C>();
-  constexpr int NT = time_nt<N, C>();
+  if (p.tv_time == 1) return tf_inv_v<N, C, 1>(p, z2, v, tw);
+  if (p.tv_time == 2) return tf_inv_v<N, C, 2>(p, z2, v, tw);
+  return tf_inv_v<N, C, 0>(p, z2, v, tw);
+}
+
+template <int LB, typename C, int V>
+static int tf_fwd_bs_v(const Plan& p, const double* v, void* z1, const C* tw, const C* w,
+                       const C* bh) {
+  constexpr int NB = time_nb<LB, C, V>();
+  constexpr int NT = time_nt<LB, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_inv<N, NB, NT, C><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw, p.S);
+  k_time_fwd_bs<LB, NB, NT, C><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, w, bh, p.S, p.Nt,
+                                                            p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
+}
+template <int LB, typename C, int V>
+static int tf_inv_bs_v(const Plan& p, const void* z2, double* v, const C* tw, const C* w,
+                       const C* bh) {
+  constexpr int NB = time_nb<LB, C, V>();
+  constexpr int NT = time_nt<LB, C, V>();
+  const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
+  k_time_inv_bs<LB, NB, NT, C><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw, w, bh, p.S,
+                                                             p.Nt, p.live);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+template <int LB, typename C>
+static int tf_fwd_bs(const Plan& p, const double* v, void* z1, const C* tw, const C* w,
+                     const C* bh) {
+  if (p.tv_time == 1) return tf_fwd_bs_v<LB, C, 1>(p, v, z1, tw, w, bh);
+  if (p.tv_time == 2) return tf_fwd_bs_v<LB, C, 2>(p, v, z1, tw, w, bh);
+  return tf_fwd_bs_v<LB, C, 0>(p, v, z1, tw, w, bh);
+}
+template <int LB, typename C>
+static int tf_inv_bs(const Plan& p, const void* z2, double* v, const C* tw, const C* w,
+                     const C* bh) {
+  if (p.tv_time == 1) return tf_inv_bs_v<LB, C, 1>(p, z2, v, tw, w, bh);
+  if (p.tv_time == 2) return tf_inv_bs_v<LB, C, 2>(p, z2, v, tw, w, bh);
+  return tf_inv_bs_v<LB, C, 0>(p, z2, v, tw, w, bh);
+}
+template <int LB, typename C>
+static int bs_kernel(const Plan& p) {
+  k_bs_kernel<LB><<<1, 256, 0, p.stream>>>(p.Nt, p.chirp, p.twNt, p.bhat, p.bhat32);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+#define RFDE_LB_SWITCH(FN, C, ...)                 \
+  switch (p.Lt) {                                  \
+    case 8: return FN<8, C>(__VA_ARGS__);          \
+    case 16: return FN<16, C>(__VA_ARGS__);        \
+    case 32: return FN<32, C>(__VA_ARGS__);        \
+    case 64: return FN<64, C>(__VA_ARGS__);        \
+    case 128: return FN<128, C>(__VA_ARGS__);      \
+    case 256: return FN<256, C>(__VA_ARGS__);      \
+    case 512: return FN<512, C>(__VA_ARGS__);      \
+    case 1024: return FN<1024, C>(__VA_ARGS__);    \
+    case 2048: return FN<2048, C>(__VA_ARGS__);    \
+    case 4096: return FN<4096, C>(__VA_ARGS__);    \
+    case 8192: return FN<8192, C>(__VA_ARGS__);    \
+    default: return RFDE_EINVAL;                   \
+  }
+
+int launch_bluestein_setup(const Plan& p) {
+  if (p.Lt == p.Nt) return RFDE_OK;
+  k_bs_chirp<<<(p.Nt + 255) / 256, 256, 0, p.stream>>>(p.Nt, p.chirp, p.chirp32);
+  RFDE_HIP(hipGetLastError());
+  RFDE_LB_SWITCH(bs_kernel, double2, p);
 }
 
 #define RFDE_NT_SWITCH(FN, C, ...)                 \
@@ -130,11 +349,23 @@ static int tf_inv(const Plan& p, const void* z2, double* v, const C* tw) {
   }
 
 int launch_time_fwd(const Plan& p, const double* v, void* z1) {
+  if (p.Lt != p.Nt) {
+    if (p.opts.precond_bits == 32) {
+      RFDE_LB_SWITCH(tf_fwd_bs, float2, p, v, z1, p.twNt32, p.chirp32, p.bhat32);
+    }
+    RFDE_LB_SWITCH(tf_fwd_bs, double2, p, v, z1, p.twNt, p.chirp, p.bhat);
+  }
   if (p.opts.precond_bits == 32) { RFDE_NT_SWITCH(tf_fwd, float2, p, v, z1, p.twNt32); }
   RFDE_NT_SWITCH(tf_fwd, double2, p, v, z1, p.twNt);
 }
 
 int launch_time_inv(const Plan& p, const void* z2, double* v) {
+  if (p.Lt != p.Nt) {
+    if (p.opts.precond_bits == 32) {
+      RFDE_LB_SWITCH(tf_inv_bs, float2, p, z2, v, p.twNt32, p.chirp32, p.bhat32);
+    }
+    RFDE_LB_SWITCH(tf_inv_bs, double2, p, z2, v, p.twNt, p.chirp, p.bhat);
+  }
   if (p.opts.precond_bits == 32) { RFDE_NT_SWITCH(tf_inv, float2, p, z2, v, p.twNt32); }
   RFDE_NT_SWITCH(tf_inv, double2, p, z2, v, p.twNt);
 }

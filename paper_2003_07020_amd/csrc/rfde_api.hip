@@ -25,18 +25,18 @@ static int next_pow2(int x) {
   return p;
 }
 static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+// Time levels accepted: powers of two up to 8192 (radix-16 Stockham) and any other count up to
+// 4096 (Bluestein, transform length next_pow2(2 Nt - 1) <= 8192).
+static bool nt_ok(int Nt) { return Nt >= 2 && (is_pow2(Nt) ? Nt <= 8192 : Nt <= 4096); }
+static int time_length(int Nt) { return is_pow2(Nt) ? Nt : next_pow2(2 * Nt - 1); }
 
-#define RFDE_TRY(expr)            \
-  do {                            \
-    int rc_ = (expr);             \
-    if (rc_ != RFDE_OK) return rc_; \
-  } while (0)
 
-static void free_plan(Plan* p) {
+void free_plan(Plan* p) {
   if (!p) return;
-  void* bufs[] = {p->g, p->sym, p->twL, p->twNt, p->twNt32, p->s, p->lambda, p->sigma, p->twD,
-                  p->factors, p->zf, p->vbuf, p->zbuf, p->wvec, p->xvec, p->Fvec, p->red,
-                  p->redout};
+  void* bufs[] = {p->g,      p->sym,     p->twL,  p->twNt,   p->twNt32, p->chirp, p->chirp32,
+                  p->bhat,   p->bhat32,  p->s,    p->lambda, p->sigma,  p->twD,   p->factors,
+                  p->zf,     p->vbuf,    p->zbuf, p->wvec,   p->xvec,   p->Fvec,  p->red,
+                  p->redout,  p->set};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (p->hred) (void)hipHostFree(p->hred);
@@ -53,16 +53,17 @@ static int dalloc(T** ptr, size_t count, size_t* acc) {
   return RFDE_OK;
 }
 
-static size_t workspace_estimate(const Plan& p) {
+size_t workspace_estimate(const Plan& p) {
   const size_t N = p.N();
   const size_t m = (size_t)p.opts.restart;
   const size_t csz = p.opts.precond_bits == 32 ? 8 : 16;
   return (2 * m + 1 + 3) * N * 8 + (size_t)p.nf * p.S * csz + ((size_t)70 * 1024) * 8 +
-         (size_t)(p.L + p.Lx + p.Ly + 2 * p.Nt) * 16;
+         (size_t)(p.L + p.Lx + p.Ly + 4 * p.Lt + 3 * p.Nt) * 16;
 }
 
-// Everything common to 1D and 2D plans once the sizes are known.
-static int plan_allocate_and_setup(Plan* p) {
+// Everything common to 1D and 2D plans once the sizes are known.  factor = false leaves the
+// factor storage allocated but unfilled (a batch factors its instances together).
+int plan_allocate_and_setup(Plan* p, bool factor) {
   const auto t0 = std::chrono::steady_clock::now();
   RFDE_HIP(hipSetDevice(p->device));
   const size_t wsz = workspace_estimate(*p);
@@ -76,8 +77,14 @@ static int plan_allocate_and_setup(Plan* p) {
   const int symlen = p->dim == 1 ? p->L / 2 + 1 : (p->Lx / 2 + 1) + (p->Ly / 2 + 1);
   RFDE_TRY(dalloc(&p->sym, symlen, &ws));
   RFDE_TRY(dalloc(&p->twL, p->dim == 1 ? p->L : p->Lx + p->Ly, &ws));
-  RFDE_TRY(dalloc(&p->twNt, p->Nt, &ws));
-  RFDE_TRY(dalloc(&p->twNt32, p->Nt, &ws));
+  RFDE_TRY(dalloc(&p->twNt, p->Lt, &ws));
+  RFDE_TRY(dalloc(&p->twNt32, p->Lt, &ws));
+  if (p->Lt != p->Nt) {
+    RFDE_TRY(dalloc(&p->chirp, p->Nt, &ws));
+    RFDE_TRY(dalloc(&p->chirp32, p->Nt, &ws));
+    RFDE_TRY(dalloc(&p->bhat, p->Lt, &ws));
+    RFDE_TRY(dalloc(&p->bhat32, p->Lt, &ws));
+  }
   RFDE_TRY(dalloc(&p->s, p->Nt, &ws));
   RFDE_TRY(dalloc(&p->lambda, p->nf, &ws));
   RFDE_TRY(dalloc(&p->sigma, gl, &ws));
@@ -96,7 +103,16 @@ static int plan_allocate_and_setup(Plan* p) {
   RFDE_HIP(hipHostMalloc((void**)&p->hred, 256 * sizeof(double), hipHostMallocDefault));
   for (auto& e : p->ev) RFDE_HIP(hipEventCreate(&e));
   p->workspace_bytes = ws;
-  if (p->factor_bytes) RFDE_HIP(hipMalloc(&p->factors, p->factor_bytes));
+  if (p->factor_bytes) {
+    RFDE_HIP(hipMalloc(&p->factors, p->factor_bytes));
+    BlockSet hs{};
+    hs.count = 1;
+    hs.nf[0] = p->nf; hs.M[0] = p->M; hs.T[0] = p->T;
+    hs.fac[0] = p->factors; hs.g[0] = p->g; hs.lambda[0] = p->lambda; hs.coef[0] = p->coef;
+    RFDE_TRY(dalloc(&p->set, 1, &ws));
+    p->workspace_bytes = ws;
+    RFDE_HIP(hipMemcpy(p->set, &hs, sizeof(BlockSet), hipMemcpyHostToDevice));
+  }
 
   hipStream_t st = p->stream;
   if (p->dim == 1) {
@@ -130,16 +146,17 @@ static int plan_allocate_and_setup(Plan* p) {
       RFDE_TRY(launch_twiddles32(tf + P0, P1, st));
     }
   }
-  RFDE_TRY(launch_twiddles(p->twNt, p->Nt, st));
-  RFDE_TRY(launch_twiddles32(p->twNt32, p->Nt, st));
+  RFDE_TRY(launch_twiddles(p->twNt, p->Lt, st));
+  RFDE_TRY(launch_twiddles32(p->twNt32, p->Lt, st));
+  RFDE_TRY(launch_bluestein_setup(*p));
   RFDE_TRY(launch_time_data(p->Nt, p->eps, p->s, p->lambda, st));
-  if (p->factor_bytes) {
+  if (p->factor_bytes && factor) {
     RFDE_HIP(hipEventRecord(p->ev[0], st));
     RFDE_TRY(launch_factorize(*p));
     RFDE_HIP(hipEventRecord(p->ev[1], st));
   }
   RFDE_HIP(hipStreamSynchronize(st));
-  if (p->factor_bytes) {
+  if (p->factor_bytes && factor) {
     float t = 0.f;
     RFDE_HIP(hipEventElapsedTime(&t, p->ev[0], p->ev[1]));
     p->ms_factor = t;
@@ -160,10 +177,36 @@ static int pinv_step_b(const Plan& p, const void* z1, void* z2) {
   return launch_tau_solve(p, z1, z2);
 }
 
-static int apply_pinv(Plan& p, const double* v, double* z) {
+int apply_pinv(Plan& p, const double* v, double* z) {
   RFDE_TRY(launch_time_fwd(p, v, p.zf));
   RFDE_TRY(pinv_step_b(p, p.zf, p.zf));
   RFDE_TRY(launch_time_inv(p, p.zf, z));
+  return RFDE_OK;
+}
+
+int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M, int Nt,
+                 double T, rfde_opts o, hipStream_t stream) {
+  if (!(alpha > 1.0 && alpha <= 2.0) || !(kappa > 0.0) || !(b > a) || M < 1 || M > 4096 ||
+      !nt_ok(Nt) || !(T > 0.0) || !opts_ok(o) || !std::isfinite(alpha + kappa + a + b + T))
+    return RFDE_EINVAL;
+  p->dim = 1;
+  p->M = M; p->S = M; p->Nt = Nt; p->nf = Nt / 2 + 1; p->Lt = time_length(Nt);
+  p->alpha = alpha; p->kappa = kappa;
+  p->h = (b - a) / (M + 1);
+  p->tau = T / Nt;
+  p->eps = o.circ_eps > 0 ? o.circ_eps : std::min(0.5, 0.5 * p->tau);
+  o.circ_eps = p->eps;
+  p->coef = p->tau * kappa / std::pow(p->h, alpha);
+  p->L = std::max(16, next_pow2(2 * M - 1));
+  p->opts = o;
+  p->stream = stream;
+  if (o.spatial == RFDE_SPATIAL_TAU && !is_pow2(M + 1)) return RFDE_EUNSUPPORTED;
+  if (o.spatial == RFDE_SPATIAL_EXACT) {
+    p->T = (M + TILE - 1) / TILE;
+    p->Mp = p->T * TILE;
+    const size_t csz = o.precond_bits == 32 ? 8 : 16;
+    p->factor_bytes = (size_t)p->nf * lower_tiles(p->T) * TILE_ELEMS * csz;
+  }
   return RFDE_OK;
 }
 
@@ -208,33 +251,12 @@ int rfde_plan_create_1d(rfde_plan* plan, double alpha, double kappa, double a, d
   rfde_opts o;
   rfde_opts_default(&o);
   if (opts) o = *opts;
-  if (!(alpha > 1.0 && alpha <= 2.0) || !(kappa > 0.0) || !(b > a) || M < 1 || M > 4096 ||
-      Nt < 2 || Nt > 8192 || !is_pow2(Nt) || !(T > 0.0) || !opts_ok(o) ||
-      !std::isfinite(alpha + kappa + a + b + T))
-    return RFDE_EINVAL;
-  if (o.precond_bits == 32 && Nt > 8192) return RFDE_EINVAL;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return RFDE_ENOMEM;
-  p->dim = 1;
-  p->M = M; p->S = M; p->Nt = Nt; p->nf = Nt / 2 + 1;
-  p->alpha = alpha; p->kappa = kappa;
-  p->h = (b - a) / (M + 1);
-  p->tau = T / Nt;
-  p->eps = o.circ_eps > 0 ? o.circ_eps : std::min(0.5, 0.5 * p->tau);
-  o.circ_eps = p->eps;
-  p->coef = p->tau * kappa / std::pow(p->h, alpha);
-  p->L = std::max(16, next_pow2(2 * M - 1));
-  p->opts = o;
-  p->stream = (hipStream_t)hip_stream;
+  int rc = plan_init_1d(p, alpha, kappa, a, b, M, Nt, T, o, (hipStream_t)hip_stream);
+  if (rc != RFDE_OK) { delete p; return rc; }
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RFDE_EHIP; }
-  if (o.spatial == RFDE_SPATIAL_TAU && !is_pow2(M + 1)) { delete p; return RFDE_EUNSUPPORTED; }
-  if (o.spatial == RFDE_SPATIAL_EXACT) {
-    p->T = (M + TILE - 1) / TILE;
-    p->Mp = p->T * TILE;
-    const size_t csz = o.precond_bits == 32 ? 8 : 16;
-    p->factor_bytes = (size_t)p->nf * lower_tiles(p->T) * TILE_ELEMS * csz;
-  }
-  const int rc = plan_allocate_and_setup(p);
+  rc = plan_allocate_and_setup(p, true);
   if (rc != RFDE_OK) { free_plan(p); return rc; }
   *plan = reinterpret_cast<rfde_plan>(p);
   return RFDE_OK;
@@ -251,14 +273,15 @@ int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double 
   o.spatial = RFDE_SPATIAL_TAU;
   if (!(alpha_x > 1.0 && alpha_x <= 2.0) || !(alpha_y > 1.0 && alpha_y <= 2.0) ||
       !(kappa_x > 0.0) || !(kappa_y > 0.0) || !(bx > ax) || !(by > ay) || Mx < 1 || My < 1 ||
-      Mx > 4096 || My > 4096 || Nt < 2 || Nt > 8192 || !is_pow2(Nt) || !(T > 0.0) || !opts_ok(o))
+      Mx > 4096 || My > 4096 || !nt_ok(Nt) || !(T > 0.0) || !opts_ok(o) ||
+      !std::isfinite(alpha_x + alpha_y + kappa_x + kappa_y + ax + bx + ay + by + T))
     return RFDE_EINVAL;
   if (!is_pow2(Mx + 1) || !is_pow2(My + 1)) return RFDE_EUNSUPPORTED;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return RFDE_ENOMEM;
   p->dim = 2;
   p->Mx = Mx; p->My = My; p->M = Mx * My; p->S = Mx * My;
-  p->Nt = Nt; p->nf = Nt / 2 + 1;
+  p->Nt = Nt; p->nf = Nt / 2 + 1; p->Lt = time_length(Nt);
   p->alpha_x = alpha_x; p->alpha_y = alpha_y; p->kappa_x = kappa_x; p->kappa_y = kappa_y;
   p->hx = (bx - ax) / (Mx + 1);
   p->hy = (by - ay) / (My + 1);
@@ -272,7 +295,7 @@ int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double 
   p->opts = o;
   p->stream = (hipStream_t)hip_stream;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RFDE_EHIP; }
-  const int rc = plan_allocate_and_setup(p);
+  const int rc = plan_allocate_and_setup(p, true);
   if (rc != RFDE_OK) { free_plan(p); return rc; }
   *plan = reinterpret_cast<rfde_plan>(p);
   return RFDE_OK;

@@ -12,6 +12,12 @@
     if (e_ != hipSuccess) return rfde::hip_fail(e_, #expr, __FILE__, __LINE__); \
   } while (0)
 
+#define RFDE_TRY(expr)              \
+  do {                              \
+    int rc_ = (expr);               \
+    if (rc_ != RFDE_OK) return rc_; \
+  } while (0)
+
 namespace rfde {
 
 int hip_fail(hipError_t e, const char* what, const char* file, int line);
@@ -23,10 +29,35 @@ constexpr int TILE_ELEMS = TILE * TILE;
 __host__ __device__ inline size_t lower_tiles(int T) { return (size_t)T * (T + 1) / 2; }
 __host__ __device__ inline size_t tile_index(int i, int j) { return (size_t)i * (i + 1) / 2 + j; }
 
+// Shifted-block families handled by one factor or solve launch: a plan's own blocks, or those
+// of every instance of a batch wave.  Lives in device memory.
+constexpr int MAX_BATCH = 64;
+struct BlockSet {
+  int count;
+  int nf[MAX_BATCH];                 // blocks (frequencies) of family k
+  int M[MAX_BATCH];                  // order
+  int T[MAX_BATCH];                  // tile count, ceil(M / 64)
+  void* fac[MAX_BATCH];              // nf x lower_tiles(T) x 4096 complex
+  const double* g[MAX_BATCH];        // g_0..g_{M-1}
+  const double2* lambda[MAX_BATCH];  // lambda_0..lambda_{nf-1}
+  double coef[MAX_BATCH];            // tau kappa / h^alpha
+  const int* live[MAX_BATCH];        // family k is skipped while *live[k] == 0 (NULL: always on)
+};
+
+// Work items of one launch, numbered family by family: family fam[k] of the BlockSet owns items
+// [start[k], start[k+1]).  Passed by value.
+struct ItemMap {
+  int cnt = 0;
+  int start[MAX_BATCH + 1];
+  int fam[MAX_BATCH];
+  int total() const { return start[cnt]; }
+};
+
 struct Plan {
   int dim = 1;
   int M = 0, Mx = 0, My = 0, S = 0;   // S = spatial unknowns per time level
   int Nt = 0, nf = 0;                 // nf = Nt/2 + 1
+  int Lt = 0;                         // time transform length: Nt, or the Bluestein length
   int L = 0, Lx = 0, Ly = 0;
   int Mp = 0, T = 0;                  // padded order and tile count of the factored blocks
   double alpha = 0, alpha_x = 0, alpha_y = 0;
@@ -36,19 +67,32 @@ struct Plan {
   rfde_opts opts{};
   hipStream_t stream = nullptr;
   int device = 0;
+  // Batch member: per-instance kernels of the iteration return at once while *live == 0
+  // (the instance has converged in the current restart cycle).  NULL for ordinary plans.
+  const int* live = nullptr;
+  // Launch-shape variants (chosen by the tuner; 0 = the built-in default):
+  //   tv_time:   time FFTs with NB >> tv_time transforms per workgroup (tv_time in 0..2)
+  //   tv_matvec: 0 default, 1 the other workgroup size, 2 largest FFT radix 8 instead of 16
+  //   trsv_cap:  0 one workgroup per block; c > 0 at most c persistent workgroups
+  int tv_time = 0, tv_matvec = 0, trsv_cap = 0;
 
   // setup data (device)
   double* g = nullptr;       // 1D: M; 2D: Mx then My
   double* sym = nullptr;     // 1D: L/2+1; 2D: Lx/2+1 then Ly/2+1 (scaled by coef / L)
   double2* twL = nullptr;    // twiddles exp(-2 pi i m / L); 2D: Lx table then Ly table
-  double2* twNt = nullptr;   // twiddles exp(-2 pi i m / Nt)
+  double2* twNt = nullptr;   // twiddles exp(-2 pi i m / Lt)
   float2* twNt32 = nullptr;  // FP32 copy for the FP32 preconditioner
+  double2* chirp = nullptr;  // Bluestein (Nt not a power of two): w_k = exp(i pi k^2 / Nt), Nt
+  float2* chirp32 = nullptr;
+  double2* bhat = nullptr;   // Bluestein: DFT of the conjugate chirp kernel / Lt, Lt entries
+  float2* bhat32 = nullptr;
   double* s = nullptr;       // Nt: eps^{j/Nt}
   double2* lambda = nullptr; // nf
   double* sigma = nullptr;   // tau eigenvalues (unscaled): 1D M; 2D Mx then My
   double2* twD = nullptr;    // DST twiddles for length 2(n+1) (tau solver)
   void* factors = nullptr;   // nf blocks x lower_tiles(T) x 4096 complex (c128 or c64)
   size_t factor_bytes = 0;
+  BlockSet* set = nullptr;   // this plan's blocks as a one-family set (device)
 
   // workspace (device)
   void* zf = nullptr;        // nf x S complex (frequency-domain work, c128 or c64)
@@ -68,6 +112,16 @@ struct Plan {
   size_t N() const { return (size_t)Nt * S; }
 };
 
+// ---- plan life cycle (rfde_api.hip) ----
+int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M, int Nt,
+                 double T, rfde_opts o, hipStream_t stream);  // sizes only, no device work
+size_t workspace_estimate(const Plan& p);
+int plan_allocate_and_setup(Plan* p, bool factor);
+void free_plan(Plan* p);
+int apply_pinv(Plan& p, const double* v, double* z);
+// what: bit 0 time FFTs, bit 1 matvec, bit 2 triangular solves (rfde_tune.hip)
+int tune_plan(Plan& p, int what, rfde_tune_report* report);
+
 // ---- launchers (all enqueue on p.stream) ----
 int launch_gk(double alpha, int n, double* g, hipStream_t st);
 int launch_twiddles(double2* tw, int n, hipStream_t st);
@@ -80,6 +134,7 @@ int launch_tau_sigma(const double* g, int n, const double2* twD, double* sigma, 
 int launch_matvec(const Plan& p, const double* v, double* y);
 int launch_rhs(const Plan& p, const double* u0, const double* f, double* F);
 
+int launch_bluestein_setup(const Plan& p);
 int launch_time_fwd(const Plan& p, const double* v, void* z1);
 int launch_time_inv(const Plan& p, const void* z2, double* v);
 int launch_widen(const Plan& p, const void* zsrc, double2* zdst);  // c64 -> c128 (FP32 plans)
@@ -87,6 +142,13 @@ int launch_narrow(const Plan& p, const double2* zsrc, void* zdst); // c128 -> c6
 
 int launch_factorize(Plan& p);
 int launch_trsv(const Plan& p, const void* zin, void* zout);
+// Factor / solve every block of the families of a set (host copy `hs`, device copy `ds`).
+// grid_cap > 0 caps the grid (persistent workgroups looping over the items); 0 launches one
+// workgroup per item.  zin/zout: one frequency-domain array per family ([nf][M] complex).
+int launch_factorize_set(const BlockSet& hs, const BlockSet* ds, int bits, int grid_cap,
+                         hipStream_t st);
+int launch_trsv_set(const BlockSet& hs, const BlockSet* ds, const void* const* zin,
+                    void* const* zout, int bits, int grid_cap, hipStream_t st);
 int launch_tau_solve(const Plan& p, const void* zin, void* zout);
 int launch_export_factor(const Plan& p, int index, void* dst);
 

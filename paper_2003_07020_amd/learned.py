@@ -200,9 +200,10 @@ class LearnedGuess:
                 lr = lr1 + 0.5 * (lr0 - lr1) * (1 + math.cos(math.pi * it / max(1, total - 1)))
                 loss = self.net.train_step(feats[idx].contiguous(), Y[idx].contiguous(), lr)
                 it += 1
-            if log and (ep + 1) % max(1, epochs // 10) == 0:
+            if (ep + 1) % max(1, epochs // 10) == 0 or ep + 1 == epochs:
                 hist.append(float(loss.item()))
-                log(f"epoch {ep + 1}/{epochs} loss {hist[-1]:.3e}")
+                if log:
+                    log(f"epoch {ep + 1}/{epochs} loss {hist[-1]:.3e}")
         return hist
 
     def guess(self, alpha, kappa, coef):

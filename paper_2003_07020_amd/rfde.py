@@ -168,6 +168,18 @@ class Plan:
         L.check(L.lib().rfde_plan_export(self._h, what, index, _ptr(t)), "rfde_plan_export")
         return t
 
+    def autotune(self) -> dict:
+        r = L.TuneReport()
+        L.check(L.lib().rfde_plan_autotune(self._h, C.byref(r)), "rfde_plan_autotune")
+        return {"time_variant": r.time_variant, "matvec_variant": r.matvec_variant,
+                "trsv_grid_cap": r.trsv_grid_cap, "from_cache": r.from_cache,
+                "ms_time": list(r.ms_time), "ms_matvec": list(r.ms_matvec),
+                "trsv_caps": list(r.trsv_caps), "ms_trsv": list(r.ms_trsv)}
+
+    def set_variants(self, time_variant: int = 0, matvec_variant: int = 0, trsv_grid_cap: int = 0):
+        L.check(L.lib().rfde_plan_set_variants(self._h, time_variant, matvec_variant,
+                                               trsv_grid_cap), "rfde_plan_set_variants")
+
     def solve(self, u0: torch.Tensor, f: torch.Tensor, U_init: torch.Tensor | None = None,
               tol: float = 0.0, out: torch.Tensor | None = None, allow_notconv: bool = False):
         _need(u0, torch.float64, self.S, "u0")
@@ -183,3 +195,73 @@ class Plan:
                            st.ms_setup, st.ms_solve, st.ms_pinv, st.ms_matvec,
                            [st.res_hist[k] for k in range(st.n_hist)])
         return U, stats, rc
+
+
+class Batch:
+    """Many independent 1D problems solved together (rfde_batch_*): instances are dicts or
+    tuples (alpha, kappa, a, b, T, M, Nt).  Marshalling only."""
+
+    def __init__(self, instances, mem_budget: int = 0, **kw):
+        inst = []
+        for x in instances:
+            if isinstance(x, dict):
+                x = (x["alpha"], x["kappa"], x.get("a", 0.0), x.get("b", 1.0), x.get("T", 1.0),
+                     x["M"], x["Nt"])
+            inst.append(L.Instance(*[float(v) for v in x[:5]], int(x[5]), int(x[6])))
+        self.sizes = [(i.M, i.Nt) for i in inst]
+        arr = (L.Instance * len(inst))(*inst)
+        o = opts(**kw)
+        h = C.c_void_p()
+        L.check(L.lib().rfde_batch_create(C.byref(h), len(inst), arr, C.byref(o), int(mem_budget),
+                                          _stream()), "rfde_batch_create")
+        self._h = h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().rfde_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> dict:
+        bi = L.BatchInfo()
+        L.check(L.lib().rfde_batch_get_info(self._h, C.byref(bi)), "rfde_batch_get_info")
+        return {k: getattr(bi, k) for k, _ in L.BatchInfo._fields_}
+
+    def wave_of(self, index: int) -> int:
+        w = L.lib().rfde_batch_wave_of(self._h, index)
+        if w < 0:
+            raise L.RfdeError(w, "rfde_batch_wave_of")
+        return w
+
+    def set_autotune(self, what: int = 3):
+        L.check(L.lib().rfde_batch_set_autotune(self._h, what), "rfde_batch_set_autotune")
+
+    def set_grid_caps(self, factor_cap: int = 0, trsv_cap: int = 0):
+        L.check(L.lib().rfde_batch_set_grid_caps(self._h, factor_cap, trsv_cap),
+                "rfde_batch_set_grid_caps")
+
+    def solve(self, u0s, fs, outs=None, allow_notconv: bool = False):
+        n = len(self.sizes)
+        if len(u0s) != n or len(fs) != n:
+            raise ValueError("one u0 and one f per instance")
+        for (M, Nt), u0, f in zip(self.sizes, u0s, fs):
+            _need(u0, torch.float64, M, "u0")
+            _need(f, torch.float64, M * Nt, "f")
+        outs = outs or [torch.empty_like(f) for f in fs]
+        P = C.c_void_p * n
+        st = (L.Stats * n)()
+        allow = (L.RFDE_OK, L.RFDE_ENOTCONV) if allow_notconv else (L.RFDE_OK,)
+        rc = L.check(L.lib().rfde_batch_solve(self._h, P(*[t.data_ptr() for t in u0s]),
+                                              P(*[t.data_ptr() for t in fs]),
+                                              P(*[t.data_ptr() for t in outs]), st),
+                     "rfde_batch_solve", allow)
+        stats = [SolveStats(s.iters, s.restarts, bool(s.converged), s.true_rel_res, s.ms_setup,
+                            s.ms_solve, s.ms_pinv, s.ms_matvec,
+                            [s.res_hist[k] for k in range(s.n_hist)]) for s in st]
+        return outs, stats, rc

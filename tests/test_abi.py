@@ -43,7 +43,8 @@ def test_invalid_arguments_rejected_without_device():
         (1.5, 1.0, 0.0, 1.0, 0, 64, 1.0),     # M < 1
         (1.5, 1.0, 0.0, 1.0, 5000, 64, 1.0),  # M too large
         (1.5, 1.0, 0.0, 1.0, 63, 1, 1.0),     # Nt < 2
-        (1.5, 1.0, 0.0, 1.0, 63, 48, 1.0),    # Nt not a power of two
+        (1.5, 1.0, 0.0, 1.0, 63, 4097, 1.0),  # Nt not a power of two and above 4096
+        (1.5, 1.0, 0.0, 1.0, 63, 16384, 1.0), # Nt above 8192
         (1.5, 1.0, 0.0, 1.0, 63, 64, 0.0),    # T <= 0
     ]
     for args in bad:
@@ -69,3 +70,22 @@ def test_invalid_arguments_rejected_without_device():
                                1.0, None, None)
     assert rc == capi.RFDE_EUNSUPPORTED
     assert L.rfde_strerror(capi.RFDE_ENAN).decode().startswith("non-finite")
+
+
+def test_batch_rejects_invalid_arguments_without_device():
+    from paper_2003_07020_amd import capi
+    L = capi.lib()
+    h = C.c_void_p()
+    good = capi.Instance(1.5, 1.0, 0.0, 1.0, 1.0, 63, 64)
+    bad = capi.Instance(1.5, 1.0, 0.0, 1.0, 1.0, 63, 4097)
+    arr = (capi.Instance * 2)(good, bad)
+    assert L.rfde_batch_create(C.byref(h), 0, arr, None, 0, None) == capi.RFDE_EINVAL
+    assert L.rfde_batch_create(C.byref(h), 2, None, None, 0, None) == capi.RFDE_EINVAL
+    assert L.rfde_batch_create(C.byref(h), 2, arr, None, 0, None) == capi.RFDE_EINVAL
+    assert h.value is None
+    o = capi.Opts()
+    L.rfde_opts_default(C.byref(o))
+    o.spatial = 1
+    assert L.rfde_batch_create(C.byref(h), 1, arr, C.byref(o), 0, None) == capi.RFDE_EUNSUPPORTED
+    assert L.rfde_batch_solve(None, None, None, None, None) == capi.RFDE_EINVAL
+    assert L.rfde_batch_destroy(None) == capi.RFDE_OK

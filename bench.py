@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="1d_M4095_Nt1024",
                     choices=["1d_M4095_Nt1024", "1d_M63_Nt64"])
-    ap.add_argument("--forms", default="fp64,fp32,learned,batched")
+    ap.add_argument("--forms", default="fp64,fp32,tau,learned,batched")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--alphas", default="")
     ap.add_argument("--pinv-reps", type=int, default=10)
@@ -71,7 +71,7 @@ def event_ms(fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def measure_form(bits, args, W, alphas, inputs, dev):
+def measure_form(bits, args, W, alphas, inputs, dev, spatial="exact"):
     """Time K steps of (setup + solve) for every alpha, then P^-1, step (b) and the matvec."""
     import torch
 
@@ -83,7 +83,8 @@ def measure_form(bits, args, W, alphas, inputs, dev):
     def one_step(record=None):
         for a, u0d, fd, _, _ in inputs:
             t0 = time.perf_counter()
-            p = Plan.create_1d(a, kappa, 0.0, 1.0, M, Nt, T, tol=1e-8, precond_bits=bits)
+            p = Plan.create_1d(a, kappa, 0.0, 1.0, M, Nt, T, tol=1e-8, precond_bits=bits,
+                               spatial=spatial)
             _, st, _ = p.solve(u0d, fd, out=U)
             t1 = time.perf_counter()
             if record is not None:
@@ -105,7 +106,8 @@ def measure_form(bits, args, W, alphas, inputs, dev):
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
 
     a_mid = alphas[len(alphas) // 2]
-    p = Plan.create_1d(a_mid, kappa, 0.0, 1.0, M, Nt, T, tol=1e-8, precond_bits=bits)
+    p = Plan.create_1d(a_mid, kappa, 0.0, 1.0, M, Nt, T, tol=1e-8, precond_bits=bits,
+                       spatial=spatial)
     info = dict(p.info)
     g = torch.Generator(device=dev).manual_seed(7)
     v = torch.randn(Nt * M, dtype=torch.float64, device=dev, generator=g)
@@ -128,10 +130,12 @@ def measure_form(bits, args, W, alphas, inputs, dev):
     nf = info["n_freq"]
     flops_factor = nf * (4.0 / 3.0) * float(M) ** 3
     ms_factor = float(np.mean([r["ms_factor"] for r in recs]))
-    achieved = flops_factor / (ms_factor * 1e-3) / 1e12
+    achieved = flops_factor / (ms_factor * 1e-3) / 1e12 if ms_factor > 0 else None
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     esz = 8 if fp32 else 16
-    bytes_b = nf * float(M) * M * esz
+    # exact: the LDL^T factors are streamed (16 M^2 bytes per block for complex128);
+    # tau: the half spectrum is read and written by the DST solves (2 x 16 B per entry)
+    bytes_b = nf * float(M) * M * esz if spatial == "exact" else 2.0 * nf * M * 16
     # step (b) is timed through the C ABI; for FP32 plans that call also converts c128 <-> c64
     # around the solves (about 0.1% of its bytes at this size).
     N = float(Nt) * M
@@ -154,10 +158,12 @@ def measure_form(bits, args, W, alphas, inputs, dev):
     return dict(
         value=float(np.mean([r["ms_total"] for r in recs])), ms_per_step=ms_per_step, recs=recs,
         sols=sols, ms_pinv=ms_pinv, ms_stepb=ms_stepb, ms_mv=ms_mv, info=info, kernels=kernels,
-        roofline={"kernel": "k_ldlt_diag+k_ldlt_panel (factorisation)", "bound": "mfma",
-                  "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                  "frac": round(achieved / peak, 4), "traffic": None},
-        roofline_step_b={"kernel": "k_trsv", "bound": "hbm",
+        roofline=None if achieved is None else {
+            "kernel": "k_ldlt_diag+k_ldlt_panel (factorisation)", "bound": "mfma",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None},
+        roofline_step_b={"kernel": "k_trsv" if spatial == "exact" else "k_dst_rows (tau)",
+                         "bound": "hbm",
                          "achieved": round(bytes_b / (ms_stepb * 1e-3) / 1e9, 1),
                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": round(bytes_b / (ms_stepb * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
@@ -343,7 +349,10 @@ def main():
     learned = measure_learned(args, dev) if "learned" in forms else None
     batched = measure_batched(args, dev) if "batched" in forms else None
     forms = [f for f in forms if f not in ("learned", "batched")]
-    results = {f: measure_form(32 if f == "fp32" else 64, args, W, alphas, inputs, dev)
+    # fp64: the plain exact-LDL^T form; fp32: its FP32 preconditioner; tau: the paper's own step
+    # (b) (DST-I diagonalisation of the tau approximation, no factors), FP64
+    results = {f: measure_form(32 if f == "fp32" else 64, args, W, alphas, inputs, dev,
+                               spatial="tau" if f == "tau" else "exact")
                for f in forms}
     base = results[forms[0]]
     a_mid = alphas[len(alphas) // 2]
@@ -358,6 +367,8 @@ def main():
                         "precond_applies_per_s": round(1e3 / r["ms_pinv"], 3),
                         "ms_factor": round(float(np.mean([x["ms_factor"] for x in r["recs"]])), 3),
                         "iters": [x["iters"] for x in r["recs"][: len(alphas)]],
+                        "ms_step_b": round(r["ms_stepb"], 4),
+                        "spatial_solver": "tau (DST-I)" if f == "tau" else "exact LDL^T",
                         "rel_err_vs_oracle": err,
                         "speedup_vs_fp64": round(base["value"] / r["value"], 3)}
     out = {

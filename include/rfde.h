@@ -160,7 +160,7 @@ typedef enum {
                               row-major matrix holding unit-lower L (strict lower part) and D
                               (diagonal) with B = L D L^T; upper part zero                      */
   RFDE_EXPORT_TAU_SIGMA = 5/* tau eigenvalues sigma_i of T (eq. (3.10)), unscaled: M doubles
-                              (2D: Mx then My)                                                */
+                              (2D: Mx then My); plans with spatial = TAU only, else EINVAL    */
 } rfde_export_what;
 
 /* Copy plan data into the device buffer dst (sizes above).  index: block for FACTOR.  async. */

@@ -89,6 +89,72 @@ template <typename C> struct WaveAcc {
   typename mma<C>::V re[2][2], im[2][2];
 };
 
+// The long K loop of the tile update forms complex products with three real products instead
+// of four (the 3M method): for x = a b with a = ar + i ai, b = br + i bi,
+//   p1 = ar br,  p2 = ai bi,  p3 = (ar + ai)(br + bi),  Re x = p1 - p2,  Im x = p3 - p1 - p2,
+// accumulated separately over K.  The initial value B_ij enters as p1 = Re B, p2 = 0,
+// p3 = Re B + Im B.  Rounding stays normwise at the unit roundoff times the operand norms.
+template <typename C> struct WaveAcc3 {
+  typename mma<C>::V p1[2][2], p2[2][2], p3[2][2];
+};
+
+template <typename C>
+__device__ __forceinline__ void acc3_init(WaveAcc3<C>& a, int i, int j,
+                                          const double* __restrict__ g, double coef, double2 lam,
+                                          int M) {
+  using R = typename mma<C>::R;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1, l16 = lane & 15;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
+        const int c = wc * 32 + bj * 16 + l16;
+        const double2 b = shifted_entry(g, coef, lam, M, i * TILE + r, j * TILE + c);
+        a.p1[bi][bj][e] = (R)b.x;
+        a.p2[bi][bj][e] = (R)0;
+        a.p3[bi][bj][e] = (R)(b.x + b.y);
+      }
+}
+
+template <typename C>
+__device__ __forceinline__ void acc3_finish(const WaveAcc3<C>& a, WaveAcc<C>& acc) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      acc.re[bi][bj] = a.p1[bi][bj] - a.p2[bi][bj];
+      acc.im[bi][bj] = a.p3[bi][bj] - a.p1[bi][bj] - a.p2[bi][bj];
+    }
+}
+
+// One K step of 4: A entries na (the -(L_ik d_k) values) for the wave's two row blocks, B
+// entries b (L_jk) for its two column blocks.
+template <typename C>
+__device__ __forceinline__ void acc3_step(WaveAcc3<C>& a, const typename mma<C>::R (&nar)[2],
+                                          const typename mma<C>::R (&nai)[2],
+                                          const typename mma<C>::R (&br)[2],
+                                          const typename mma<C>::R (&bim)[2]) {
+  using R = typename mma<C>::R;
+  R sa[2], sb[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    sa[q] = nar[q] + nai[q];
+    sb[q] = br[q] + bim[q];
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      a.p1[bi][bj] = mma<C>::fma(nar[bi], br[bj], a.p1[bi][bj]);
+      a.p2[bi][bj] = mma<C>::fma(nai[bi], bim[bj], a.p2[bi][bj]);
+      a.p3[bi][bj] = mma<C>::fma(sa[bi], sb[bj], a.p3[bi][bj]);
+    }
+}
+
 // acc = B_ij - sum_{k<j} (L_ik D_k) L_jk^T for the 64x64 tile (i, j) of block n, operands
 // staged through LDS (used for FP32).  The K dimension (j tiles of 64 columns) is walked in chunks of KC = 16 columns.  A chunk of
 // L_ik, of L_jk (16 contiguous tile columns each, column-major tiles) and the 16 matching d_k
@@ -112,20 +178,13 @@ __device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __r
   const int lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int l16 = lane & 15, lq = lane >> 4;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
-        const int c = wc * 32 + bj * 16 + l16;
-        const double2 b = shifted_entry(g, coef, lam, M, i * TILE + r, j * TILE + c);
-        acc.re[bi][bj][e] = (R)b.x;
-        acc.im[bi][bj][e] = (R)b.y;
-      }
+  WaveAcc3<C> a3;
+  acc3_init<C>(a3, i, j, g, coef, lam, M);
   const int nchunk = j * (TILE / KC);
-  if (nchunk == 0) return;
+  if (nchunk == 0) {
+    acc3_finish<C>(a3, acc);
+    return;
+  }
   // per thread: 4 entries of each operand chunk (KC*64 = 1024 = 4 x 256) and one d
   const C* Arow = fac + tile_index(i, 0) * TILE_ELEMS;
   const C* Brow = fac + tile_index(j, 0) * TILE_ELEMS;
@@ -158,34 +217,26 @@ __device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __r
     for (int q = 0; q < KC / 4; ++q) {
       const int kk = 4 * q + lq;
       const C d = sb.D[cur][kk];
-      R nar[2], nai[2], nnai[2], br[2], bi_[2];
+      R nar[2], nai[2], br[2], bim[2];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
         const C a = sb.A[cur][kk * TILE + wr * 32 + bi * 16 + l16];
         // na = -(a d)
         nar[bi] = -(a.x * d.x - a.y * d.y);
         nai[bi] = -(a.x * d.y + a.y * d.x);
-        nnai[bi] = -nai[bi];
       }
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
         const C b = sb.B[cur][kk * TILE + wc * 32 + bj * 16 + l16];
         br[bj] = b.x;
-        bi_[bj] = b.y;
+        bim[bj] = b.y;
       }
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          acc.re[bi][bj] = mma<C>::fma(nar[bi], br[bj], acc.re[bi][bj]);
-          acc.re[bi][bj] = mma<C>::fma(nnai[bi], bi_[bj], acc.re[bi][bj]);
-          acc.im[bi][bj] = mma<C>::fma(nar[bi], bi_[bj], acc.im[bi][bj]);
-          acc.im[bi][bj] = mma<C>::fma(nai[bi], br[bj], acc.im[bi][bj]);
-        }
+      acc3_step<C>(a3, nar, nai, br, bim);
     }
     if (c + 1 < nchunk) lstore(cur ^ 1);
     __syncthreads();
   }
+  acc3_finish<C>(a3, acc);
 }
 
 // acc = B_ij - sum_{k<j} (L_ik D_k) L_jk^T, operands read by each wave straight from global
@@ -198,18 +249,8 @@ __device__ __forceinline__ void tile_update_direct(WaveAcc<C>& acc, const C* __r
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int l16 = lane & 15, lq = lane >> 4;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
-        const int c = wc * 32 + bj * 16 + l16;
-        const double2 b = shifted_entry(g, coef, lam, M, i * TILE + r, j * TILE + c);
-        acc.re[bi][bj][e] = (R)b.x;
-        acc.im[bi][bj][e] = (R)b.y;
-      }
+  WaveAcc3<C> a3;
+  acc3_init<C>(a3, i, j, g, coef, lam, M);
   for (int k = 0; k < j; ++k) {
     const C* Lik = fac + tile_index(i, k) * TILE_ELEMS;
     const C* Ljk = fac + tile_index(j, k) * TILE_ELEMS;
@@ -218,32 +259,24 @@ __device__ __forceinline__ void tile_update_direct(WaveAcc<C>& acc, const C* __r
     for (int q = 0; q < 16; ++q) {
       const int kk = 4 * q + lq;
       const C d = Dk[kk * (TILE + 1)];
-      R nar[2], nai[2], nnai[2], br[2], bi_[2];
+      R nar[2], nai[2], br[2], bim[2];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
         const C a = Lik[kk * TILE + wr * 32 + bi * 16 + l16];
         // na = -(a d)
         nar[bi] = -(a.x * d.x - a.y * d.y);
         nai[bi] = -(a.x * d.y + a.y * d.x);
-        nnai[bi] = -nai[bi];
       }
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
         const C b = Ljk[kk * TILE + wc * 32 + bj * 16 + l16];
         br[bj] = b.x;
-        bi_[bj] = b.y;
+        bim[bj] = b.y;
       }
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          acc.re[bi][bj] = mma<C>::fma(nar[bi], br[bj], acc.re[bi][bj]);
-          acc.re[bi][bj] = mma<C>::fma(nnai[bi], bi_[bj], acc.re[bi][bj]);
-          acc.im[bi][bj] = mma<C>::fma(nar[bi], bi_[bj], acc.im[bi][bj]);
-          acc.im[bi][bj] = mma<C>::fma(nai[bi], br[bj], acc.im[bi][bj]);
-        }
+      acc3_step<C>(a3, nar, nai, br, bim);
     }
   }
+  acc3_finish<C>(a3, acc);
 }
 
 // Write the wave accumulators into an LDS tile (column-major, leading dimension LDSLD).
@@ -283,7 +316,7 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(const BlockSet* __restrict__ 
   const int M = set->M[fm];
   const double* __restrict__ g = set->g[fm];
   const double coef = set->coef[fm];
-  C* fac = (C*)set->fac[fm] + (size_t)n * lower_tiles(set->T[fm]) * TILE_ELEMS;
+  C* fac = (C*)map.fac[slot] + (size_t)n * lower_tiles(set->T[fm]) * TILE_ELEMS;
   C* Djj = fac + tile_index(j, j) * TILE_ELEMS;
   const int t = threadIdx.x;
   if (j == 0) {
@@ -358,7 +391,7 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
   const int lb = item - map.start[slot];
   const int n = lb / per, i = j + 1 + lb % per;
   const double2 lamn = set->lambda[fm][n];
-  C* fac = (C*)set->fac[fm] + (size_t)n * lower_tiles(T) * TILE_ELEMS;
+  C* fac = (C*)map.fac[slot] + (size_t)n * lower_tiles(T) * TILE_ELEMS;
   {
     WaveAcc<C> acc;
     if constexpr (sizeof(C) == 8) {
@@ -512,6 +545,7 @@ static ItemMap column_map(const BlockSet& hs, int j, bool panel) {
     const int per = panel ? hs.T[k] - 1 - j : (hs.T[k] > j ? 1 : 0);
     if (per <= 0) continue;
     m.fam[m.cnt] = k;
+    m.fac[m.cnt] = hs.fac[k];
     m.start[m.cnt + 1] = m.start[m.cnt] + hs.nf[k] * per;
     ++m.cnt;
   }
@@ -597,7 +631,7 @@ __global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, 
   if (set->live[fm] && *set->live[fm] == 0) return;  // uniform across the workgroup
   const int n = item - map.start[slot];
   const int M = set->M[fm], T = set->T[fm];
-  const C* fac = (const C*)set->fac[fm] + (size_t)n * lower_tiles(T) * TILE_ELEMS;
+  const C* fac = (const C*)map.fac[slot] + (size_t)n * lower_tiles(T) * TILE_ELEMS;
   const C* zin = (const C*)io.in[fm];
   C* zout = (C*)io.out[fm];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -729,6 +763,7 @@ int launch_trsv_set(const BlockSet& hs, const BlockSet* ds, const void* const* z
     io.out[k] = zout[k];
     if (!zin[k] || !zout[k]) continue;  // family skipped in this launch
     m.fam[m.cnt] = k;
+    m.fac[m.cnt] = hs.fac[k];
     m.start[m.cnt + 1] = m.start[m.cnt] + hs.nf[k];
     ++m.cnt;
   }

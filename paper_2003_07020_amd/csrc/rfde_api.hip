@@ -119,7 +119,8 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
     RFDE_TRY(launch_gk(p->alpha, p->M, p->g, st));
     RFDE_TRY(launch_twiddles(p->twL, p->L, st));
     RFDE_TRY(launch_symbol(p->g, p->M, p->L, p->coef / p->L, p->twL, p->sym, st));
-    RFDE_TRY(launch_tau_sigma(p->g, p->M, nullptr, p->sigma, st));
+    if (p->opts.spatial == RFDE_SPATIAL_TAU)
+      RFDE_TRY(launch_tau_sigma(p->g, p->M, nullptr, p->sigma, st));
   } else {
     RFDE_TRY(launch_gk(p->alpha_x, p->Mx, p->g, st));
     RFDE_TRY(launch_gk(p->alpha_y, p->My, p->g + p->Mx, st));
@@ -354,6 +355,7 @@ int rfde_plan_export(rfde_plan plan, int what, int index, void* dst) {
       if (!p->factor_bytes || index < 0 || index >= p->nf) return RFDE_EINVAL;
       return launch_export_factor(*p, index, dst);
     case RFDE_EXPORT_TAU_SIGMA:
+      if (p->opts.spatial != RFDE_SPATIAL_TAU) return RFDE_EINVAL;  // only tau plans hold sigma
       RFDE_HIP(hipMemcpyAsync(dst, p->sigma, gl * sizeof(double), hipMemcpyDeviceToDevice, st));
       return RFDE_OK;
     default:

@@ -45,11 +45,14 @@ struct BlockSet {
 };
 
 // Work items of one launch, numbered family by family: family fam[k] of the BlockSet owns items
-// [start[k], start[k+1]).  Passed by value.
+// [start[k], start[k+1]).  Passed by value; it also carries each slot's factor pointer, since
+// pointers read from kernel arguments are known to be global-memory pointers (global loads),
+// while pointers read from the device-memory BlockSet would be addressed as generic (flat).
 struct ItemMap {
   int cnt = 0;
   int start[MAX_BATCH + 1];
   int fam[MAX_BATCH];
+  void* fac[MAX_BATCH];
   int total() const { return start[cnt]; }
 };
 

@@ -265,3 +265,14 @@ class Batch:
                             s.ms_solve, s.ms_pinv, s.ms_matvec,
                             [s.res_hist[k] for k in range(s.n_hist)]) for s in st]
         return outs, stats, rc
+
+
+def solve(alpha: float, kappa: float, domain, M: int, Nt: int, T: float, u0: torch.Tensor,
+          f: torch.Tensor, tol: float = 1e-8, U_init: torch.Tensor | None = None, **kw):
+    """One-call 1D solve (plan, solve, release): the problem of eq. (1.1) on (a, b) x (0, T]
+    with M interior points and Nt BDF2 steps; u0 [M], f [Nt][M] FP64 device tensors (f at
+    t_1..t_Nt).  Returns (U [Nt * M], SolveStats)."""
+    a, b = domain
+    with Plan.create_1d(alpha, kappa, a, b, M, Nt, T, tol=tol, **kw) as p:
+        U, st, _ = p.solve(u0, f, U_init=U_init)
+    return U, st

@@ -115,3 +115,16 @@ def test_bitwise_reproducible():
     a, b, c = to_host(U1), to_host(U2), to_host(U3)
     assert np.array_equal(a, b) and np.array_equal(a, c)
     assert st1.res_hist == st2.res_hist == st3.res_hist
+
+
+def test_one_call_solve():
+    from paper_2003_07020_amd import rfde
+    banner("rfde.solve")
+    M, Nt, alpha, kappa = 50, 12, 1.4, 0.9
+    u0, f, _ = gen1d(31, M, Nt)
+    U, st = rfde.solve(alpha, kappa, (0.0, 1.0), M, Nt, 1.0, to_dev(u0), to_dev(f.ravel()),
+                       tol=1e-11)
+    h, tau = aa.mesh(0.0, 1.0, M, 1.0, Nt)
+    assert st.converged
+    assert rel_max(to_host(U).reshape(Nt, M),
+                   aa.bdf2_march(u0, f, aa.jacobian_A(alpha, kappa, h, M), tau)) < 1e-9

@@ -1,6 +1,5 @@
 """Launch-shape variants and the tuner: every variant of the time FFTs, the matvec and the
-triangular solves computes the same result as the default shape (bitwise where the arithmetic
-is the same, within the FFT tolerance of the oracle where the radix changes), and a tuned plan
+triangular solves computes the same result as the default shape (to rounding), and a tuned plan
 still solves to the oracle's answer."""
 import numpy as np
 import pytest
@@ -43,13 +42,14 @@ def test_variants_agree(alpha, M, Nt, bits):
                     y_or = aa.apply_all_at_once(to_host(v).reshape(Nt, M), A, tau)
                     assert rel_max(out[3].reshape(Nt, M), y_or) < TOL_FFT
                     continue
-                assert np.array_equal(out[0], ref["z1"]), (tv, mv, cap)
-                assert np.array_equal(out[1], ref["z2"]), (tv, mv, cap)
-                assert np.array_equal(out[2], ref["vc"]), (tv, mv, cap)
-                if mv == 2:   # radix-8 passes: other rounding, same transform
-                    assert rel_max(out[3], ref["y"]) < TOL_FFT, (tv, mv, cap)
-                else:
-                    assert np.array_equal(out[3], ref["y"]), (tv, mv, cap)
+                # the same operations on each element; only the compiler's choice of fused
+                # multiply-adds (and, for matvec variant 2, the radix) may differ between the
+                # instantiations, so results agree to rounding
+                tol = TOL_FFT if bits == 64 else 1e-5
+                assert rel_max(out[0], ref["z1"]) < tol, (tv, mv, cap)
+                assert rel_max(out[1], ref["z2"]) < tol, (tv, mv, cap)
+                assert rel_max(out[2], ref["vc"]) < tol, (tv, mv, cap)
+                assert rel_max(out[3], ref["y"]) < TOL_FFT, (tv, mv, cap)
 
 
 @pytest.mark.parametrize("bits", [64, 32])

@@ -60,6 +60,34 @@ def workload(name):
     return dict(SMALL_1D, alphas=(SMALL_1D["alpha"],))
 
 
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "traffic_kernels_1d_M4095_Nt1024_fp64.md")
+
+
+def pmc_traffic():
+    """HBM bytes per launch of the FP64 factor-panel and triangular-solve kernels, from the
+    committed rocprofv3 PMC summary -- only while the kernel sources still hash to the
+    profiled version (else None: the counters no longer describe these kernels)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        blob = json.loads(text.split("```json\n", 1)[1].split("\n```", 1)[0])
+        h = hashlib.sha256()
+        root = os.path.dirname(os.path.abspath(__file__))
+        for f in blob["sources"]:
+            h.update(open(os.path.join(root, f), "rb").read())
+        if h.hexdigest() != blob["sources_sha256"]:
+            return None
+        return {k: v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"]
+                for k, v in blob.items() if isinstance(v, dict)}
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def event_ms(fn, reps, stream):
     import torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -189,10 +217,12 @@ def measure_learned(args, dev):
     feats, Y, nsolve = lg.generate(draws)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
+    progress(f"learned: {nsolve} training solves in {t_gen:.1f} s")
     t0 = time.perf_counter()
     hist = lg.train(feats, Y, epochs=args.learned_epochs, batch=32, lr0=args.learned_lr, lr1=2e-5)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    progress(f"learned: trained in {t_train:.1f} s")
     del Y
     rec = []
     for i in range(args.learned_heldout):
@@ -248,6 +278,7 @@ def measure_batched(args, dev):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b = Batch(inst, tol=1e-8, precond_bits=32)
+    b.set_autotune(3)   # time-FFT and matvec launch shapes per instance shape (cached)
     _, stats, _ = b.solve(u0s, fs, outs)
     torch.cuda.synchronize()
     ms_batch = (time.perf_counter() - t0) * 1e3
@@ -269,8 +300,11 @@ def measure_batched(args, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3, iters
 
+    progress(f"batched: one call {ms_batch:.0f} ms")
     ms32, it32 = one_by_one(32)
+    progress(f"batched: one by one fp32 {ms32:.0f} ms")
     ms64, it64 = one_by_one(64)
+    progress(f"batched: one by one fp64 {ms64:.0f} ms")
     # the two smallest instances against the oracle's march
     from oracle import allatonce as aa
     errs = []
@@ -347,13 +381,19 @@ def main():
         inputs.append((a, torch.from_numpy(u0).to(dev), torch.from_numpy(f.ravel()).to(dev), u0, f))
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     learned = measure_learned(args, dev) if "learned" in forms else None
+    if learned is not None:
+        progress("learned form done")
     batched = measure_batched(args, dev) if "batched" in forms else None
+    if batched is not None:
+        progress("batched form done")
     forms = [f for f in forms if f not in ("learned", "batched")]
     # fp64: the plain exact-LDL^T form; fp32: its FP32 preconditioner; tau: the paper's own step
     # (b) (DST-I diagonalisation of the tau approximation, no factors), FP64
-    results = {f: measure_form(32 if f == "fp32" else 64, args, W, alphas, inputs, dev,
-                               spatial="tau" if f == "tau" else "exact")
-               for f in forms}
+    results = {}
+    for f in forms:
+        results[f] = measure_form(32 if f == "fp32" else 64, args, W, alphas, inputs, dev,
+                                  spatial="tau" if f == "tau" else "exact")
+        progress(f"form {f} done")
     base = results[forms[0]]
     a_mid = alphas[len(alphas) // 2]
     cpu, Uref = (None, None) if args.no_cpu_baseline else cpu_baseline(inputs, a_mid, M, Nt,
@@ -371,6 +411,12 @@ def main():
                         "spatial_solver": "tau (DST-I)" if f == "tau" else "exact LDL^T",
                         "rel_err_vs_oracle": err,
                         "speedup_vs_fp64": round(base["value"] / r["value"], 3)}
+    traffic = pmc_traffic() if forms[0] == "fp64" else None
+    if traffic and base["roofline"] is not None:
+        base["roofline"]["traffic"] = traffic.get("k_ldlt_panel_fp64")
+        base["roofline"]["traffic_unit"] = "bytes per k_ldlt_panel launch (PMC)"
+        base["roofline_step_b"]["traffic"] = traffic.get("k_trsv_fp64")
+        base["roofline_step_b"]["traffic_unit"] = "bytes per launch (PMC)"
     out = {
         "metric": METRIC,
         "value": round(base["value"], 3),

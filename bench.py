@@ -281,6 +281,13 @@ def measure_batched(args, dev):
     b.set_autotune(3)   # time-FFT and matvec launch shapes per instance shape (cached)
     _, stats, _ = b.solve(u0s, fs, outs)
     torch.cuda.synchronize()
+    ms_first = (time.perf_counter() - t0) * 1e3
+    info_first = b.info
+    # the same batch again: device memory already mapped, shapes tuned (the steady state of a
+    # solver that serves such batches)
+    t0 = time.perf_counter()
+    _, stats, _ = b.solve(u0s, fs, outs)
+    torch.cuda.synchronize()
     ms_batch = (time.perf_counter() - t0) * 1e3
     info = b.info
     b.destroy()
@@ -318,7 +325,10 @@ def measure_batched(args, dev):
     return {"workload": f"1d_batch{len(inst)}_uneven", "instances": len(inst),
             "waves": info["waves"], "max_wave": info["max_wave"],
             "device_GB_largest_wave": round(info["device_bytes_max"] / 1e9, 2),
-            "ms_total": round(ms_batch, 1), "ms_setup": round(info["ms_setup"], 1),
+            "ms_total": round(ms_batch, 1), "ms_total_first_call": round(ms_first, 1),
+            "ms_plans_first_call": round(info_first["ms_plans"], 1),
+            "ms_setup": round(info["ms_setup"], 1),
+            "ms_plans": round(info["ms_plans"], 1), "ms_tune": round(info["ms_tune"], 1),
             "ms_factor": round(info["ms_factor"], 1), "ms_solve": round(info["ms_solve"], 1),
             "factor_TFLOPs": round(flops / (info["ms_factor"] * 1e-3) / 1e12, 2),
             "graph_launches": info["graph_launches"],

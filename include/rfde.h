@@ -257,6 +257,8 @@ typedef struct {
   size_t instance_bytes_max; /* estimated device bytes of the largest instance                 */
   size_t device_bytes_max;/* device bytes actually held by the largest wave of the last solve */
   double ms_setup;        /* last rfde_batch_solve, summed over waves: plan setup + factors   */
+  double ms_plans;        /* ... of which: creating the instances' plans (allocation, g_k,   */
+  double ms_tune;         /*     symbols, lambda) and tuning their launch shapes              */
   double ms_factor;       /* ... device time of the factorisation launches (HIP events)       */
   double ms_solve;        /* ... right-hand sides + FGMRES + true residuals (wall)            */
   int graph_launches;     /* ... Arnoldi-step graphs launched                                 */
@@ -266,10 +268,12 @@ typedef struct {
  * Create a batch of `count` instances.  Every instance is validated as rfde_plan_create_1d
  * validates its arguments (EINVAL, EUNSUPPORTED); opts apply to all of them (spatial must be
  * RFDE_SPATIAL_EXACT, else EUNSUPPORTED).  mem_budget = device bytes the batch may hold at
- * once (0: 95% of the free memory); instances are packed, largest first, into waves of at most
- * 64 instances that fit it; ENOMEM if one instance alone does not fit.  No device memory is
- * held between calls.  hip_stream: the caller's stream (rfde_batch_solve synchronises with it
- * on entry and runs on a stream of its own, which graph capture needs).
+ * once (0: a quarter of the free memory, or the largest instance if that is more; never more
+ * than 95% of it); instances are packed, largest first, into waves of at most 64 instances
+ * that fit it; ENOMEM if one instance alone does not fit.  The first rfde_batch_solve maps one
+ * device buffer of the largest wave's size, which all waves and later solves reuse; it is
+ * released by rfde_batch_destroy.  hip_stream: the caller's stream (rfde_batch_solve
+ * synchronises with it on entry and runs on a stream of its own, which graph capture needs).
  */
 int rfde_batch_create(rfde_batch* batch, int count, const rfde_instance* inst,
                       const rfde_opts* opts, size_t mem_budget, void* hip_stream);

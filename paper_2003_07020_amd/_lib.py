@@ -54,6 +54,7 @@ class BatchInfo(C.Structure):
                 ("budget_bytes", C.c_size_t), ("wave_bytes_max", C.c_size_t),
                 ("instance_bytes_max", C.c_size_t),
                 ("device_bytes_max", C.c_size_t), ("ms_setup", C.c_double),
+                ("ms_plans", C.c_double), ("ms_tune", C.c_double),
                 ("ms_factor", C.c_double), ("ms_solve", C.c_double),
                 ("graph_launches", C.c_int)]
 

@@ -37,18 +37,34 @@ void free_plan(Plan* p) {
                   p->bhat,   p->bhat32,  p->s,    p->lambda, p->sigma,  p->twD,   p->factors,
                   p->zf,     p->vbuf,    p->zbuf, p->wvec,   p->xvec,   p->Fvec,  p->red,
                   p->redout,  p->set};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+  if (!p->arena)
+    for (void* b : bufs)
+      if (b) (void)hipFree(b);
   if (p->hred) (void)hipHostFree(p->hred);
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
 }
 
+// Device buffer of `bytes` for plan p: from its arena (256-byte aligned) or hipMalloc.
+static int palloc(Plan* p, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (p->arena) {
+    Arena& a = *p->arena;
+    const size_t off = (a.used + 255) & ~(size_t)255;
+    if (off + bytes > a.size) return RFDE_ENOMEM;
+    *ptr = a.base + off;
+    a.used = off + bytes;
+    return RFDE_OK;
+  }
+  RFDE_HIP(hipMalloc(ptr, bytes));
+  return RFDE_OK;
+}
+
 template <typename T>
-static int dalloc(T** ptr, size_t count, size_t* acc) {
+static int dalloc(Plan* p, T** ptr, size_t count, size_t* acc) {
   if (count == 0) count = 1;
-  RFDE_HIP(hipMalloc((void**)ptr, count * sizeof(T)));
+  RFDE_TRY(palloc(p, (void**)ptr, count * sizeof(T)));
   if (acc) *acc += count * sizeof(T);
   return RFDE_OK;
 }
@@ -69,47 +85,47 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
   const size_t wsz = workspace_estimate(*p);
   size_t freeb = 0, totalb = 0;
   RFDE_HIP(hipMemGetInfo(&freeb, &totalb));
-  if (p->factor_bytes + wsz > freeb) return RFDE_ENOMEM;
+  if (!p->arena && p->factor_bytes + wsz > freeb) return RFDE_ENOMEM;
 
   size_t ws = 0;
   const int gl = p->dim == 1 ? p->M : p->Mx + p->My;
-  RFDE_TRY(dalloc(&p->g, gl, &ws));
+  RFDE_TRY(dalloc(p, &p->g, gl, &ws));
   const int symlen = p->dim == 1 ? p->L / 2 + 1 : (p->Lx / 2 + 1) + (p->Ly / 2 + 1);
-  RFDE_TRY(dalloc(&p->sym, symlen, &ws));
-  RFDE_TRY(dalloc(&p->twL, p->dim == 1 ? p->L : p->Lx + p->Ly, &ws));
-  RFDE_TRY(dalloc(&p->twNt, p->Lt, &ws));
-  RFDE_TRY(dalloc(&p->twNt32, p->Lt, &ws));
+  RFDE_TRY(dalloc(p, &p->sym, symlen, &ws));
+  RFDE_TRY(dalloc(p, &p->twL, p->dim == 1 ? p->L : p->Lx + p->Ly, &ws));
+  RFDE_TRY(dalloc(p, &p->twNt, p->Lt, &ws));
+  RFDE_TRY(dalloc(p, &p->twNt32, p->Lt, &ws));
   if (p->Lt != p->Nt) {
-    RFDE_TRY(dalloc(&p->chirp, p->Nt, &ws));
-    RFDE_TRY(dalloc(&p->chirp32, p->Nt, &ws));
-    RFDE_TRY(dalloc(&p->bhat, p->Lt, &ws));
-    RFDE_TRY(dalloc(&p->bhat32, p->Lt, &ws));
+    RFDE_TRY(dalloc(p, &p->chirp, p->Nt, &ws));
+    RFDE_TRY(dalloc(p, &p->chirp32, p->Nt, &ws));
+    RFDE_TRY(dalloc(p, &p->bhat, p->Lt, &ws));
+    RFDE_TRY(dalloc(p, &p->bhat32, p->Lt, &ws));
   }
-  RFDE_TRY(dalloc(&p->s, p->Nt, &ws));
-  RFDE_TRY(dalloc(&p->lambda, p->nf, &ws));
-  RFDE_TRY(dalloc(&p->sigma, gl, &ws));
+  RFDE_TRY(dalloc(p, &p->s, p->Nt, &ws));
+  RFDE_TRY(dalloc(p, &p->lambda, p->nf, &ws));
+  RFDE_TRY(dalloc(p, &p->sigma, gl, &ws));
   const size_t csz = p->opts.precond_bits == 32 ? 8 : 16;
-  RFDE_HIP(hipMalloc(&p->zf, (size_t)p->nf * p->S * csz));
+  RFDE_TRY(palloc(p, &p->zf, (size_t)p->nf * p->S * csz));
   ws += (size_t)p->nf * p->S * csz;
   const size_t N = p->N();
   const size_t m = (size_t)p->opts.restart;
-  RFDE_TRY(dalloc(&p->vbuf, (m + 1) * N, &ws));
-  RFDE_TRY(dalloc(&p->zbuf, m * N, &ws));
-  RFDE_TRY(dalloc(&p->wvec, N, &ws));
-  RFDE_TRY(dalloc(&p->xvec, N, &ws));
-  RFDE_TRY(dalloc(&p->Fvec, N, &ws));
-  RFDE_TRY(dalloc(&p->red, (size_t)70 * 1024, &ws));
-  RFDE_TRY(dalloc(&p->redout, 256, &ws));
+  RFDE_TRY(dalloc(p, &p->vbuf, (m + 1) * N, &ws));
+  RFDE_TRY(dalloc(p, &p->zbuf, m * N, &ws));
+  RFDE_TRY(dalloc(p, &p->wvec, N, &ws));
+  RFDE_TRY(dalloc(p, &p->xvec, N, &ws));
+  RFDE_TRY(dalloc(p, &p->Fvec, N, &ws));
+  RFDE_TRY(dalloc(p, &p->red, (size_t)70 * 1024, &ws));
+  RFDE_TRY(dalloc(p, &p->redout, 256, &ws));
   RFDE_HIP(hipHostMalloc((void**)&p->hred, 256 * sizeof(double), hipHostMallocDefault));
   for (auto& e : p->ev) RFDE_HIP(hipEventCreate(&e));
   p->workspace_bytes = ws;
   if (p->factor_bytes) {
-    RFDE_HIP(hipMalloc(&p->factors, p->factor_bytes));
+    RFDE_TRY(palloc(p, &p->factors, p->factor_bytes));
     BlockSet hs{};
     hs.count = 1;
     hs.nf[0] = p->nf; hs.M[0] = p->M; hs.T[0] = p->T;
     hs.fac[0] = p->factors; hs.g[0] = p->g; hs.lambda[0] = p->lambda; hs.coef[0] = p->coef;
-    RFDE_TRY(dalloc(&p->set, 1, &ws));
+    RFDE_TRY(dalloc(p, &p->set, 1, &ws));
     p->workspace_bytes = ws;
     RFDE_HIP(hipMemcpy(p->set, &hs, sizeof(BlockSet), hipMemcpyHostToDevice));
   }
@@ -137,7 +153,7 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
     const int P0 = p->dim == 1 ? 2 * (p->M + 1) : 2 * (p->Mx + 1);
     const int P1 = p->dim == 1 ? 0 : 2 * (p->My + 1);
     const int Ptot = P0 + P1;
-    RFDE_HIP(hipMalloc((void**)&p->twD, (size_t)Ptot * (sizeof(double2) + sizeof(float2))));
+    RFDE_TRY(palloc(p, (void**)&p->twD, (size_t)Ptot * (sizeof(double2) + sizeof(float2))));
     p->workspace_bytes += (size_t)Ptot * (sizeof(double2) + sizeof(float2));
     float2* tf = reinterpret_cast<float2*>(p->twD + Ptot);
     RFDE_TRY(launch_twiddles(p->twD, P0, st));

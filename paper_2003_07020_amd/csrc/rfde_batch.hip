@@ -286,6 +286,10 @@ struct rfde_batch_ {
   int grid_cap_factor = 0, grid_cap_trsv = 0;
   int tune = 0;                    // tune_plan flags for every instance (0: off)
   std::vector<char> conv, failed;  // outcome per instance of the last solve
+  Arena arena;                     // device memory of the waves, mapped once, reused
+  ~rfde_batch_() {
+    if (arena.base) (void)hipFree(arena.base);
+  }
 };
 
 namespace {
@@ -385,8 +389,12 @@ int solve_wave(rfde_batch_& B, const std::vector<int>& idx, const double* const*
   w.st = st;
   w.exec.assign(m, nullptr);
   const auto t0 = std::chrono::steady_clock::now();
+  B.arena.used = 0;  // the previous wave's plans are gone
   RFDE_HIP(hipMalloc((void**)&w.S, sizeof(WaveState)));
   RFDE_HIP(hipMalloc((void**)&w.ds, sizeof(BlockSet)));
+  auto ms_since = [](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+  };
   // plans (setup kernels run, factors allocated but not yet filled)
   for (int k = 0; k < cnt; ++k) {
     const rfde_instance& in = B.inst[idx[k]];
@@ -397,6 +405,7 @@ int solve_wave(rfde_batch_& B, const std::vector<int>& idx, const double* const*
     p->live = reinterpret_cast<const int*>(reinterpret_cast<const char*>(w.S) +
                                            offsetof(WaveState, live)) + k;
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RFDE_EHIP; }
+    p->arena = &B.arena;
     rc = plan_allocate_and_setup(p, false);
     if (rc != RFDE_OK) { free_plan(p); return rc; }
     w.plans.push_back(p);
@@ -425,9 +434,12 @@ int solve_wave(rfde_batch_& B, const std::vector<int>& idx, const double* const*
   RFDE_HIP(hipMemcpy(w.S, hS, sizeof(WaveState), hipMemcpyHostToDevice));
   RFDE_HIP(hipMemcpy(w.ds, &hs, sizeof(BlockSet), hipMemcpyHostToDevice));
   RFDE_HIP(hipHostMalloc((void**)&w.host, HOST_PART, hipHostMallocDefault));
+  B.info.ms_plans += ms_since(t0);
   // launch shapes of each instance's time FFTs and matvec (cached per shape)
+  const auto tt = std::chrono::steady_clock::now();
   if (B.tune & 3)
     for (Plan* p : w.plans) RFDE_TRY(tune_plan(*p, B.tune & 3, nullptr));
+  B.info.ms_tune += ms_since(tt);
   // factorisation of every block of every instance
   hipEvent_t e0, e1;
   RFDE_HIP(hipEventCreate(&e0));
@@ -624,7 +636,12 @@ int rfde_batch_create(rfde_batch* batch, int count, const rfde_instance* inst,
   if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) { delete B; return RFDE_EHIP; }
   const size_t fixed = sizeof(WaveState) + sizeof(BlockSet) + ((size_t)64 << 20);
   const size_t cap = freeb > fixed ? (size_t)((freeb - fixed) * 0.95) : 0;
-  B->budget = mem_budget ? std::min(mem_budget, cap) : cap;
+  size_t big = 0;
+  for (size_t u : B->bytes) big = std::max(big, u);
+  // default: a quarter of the free memory (or the largest instance): small instances share
+  // waves, large ones (which fill the GPU alone) take few per wave, and the memory that has to
+  // be mapped stays moderate
+  B->budget = mem_budget ? std::min(mem_budget, cap) : std::min(cap, std::max(big, cap / 4));
   // first fit, largest first, at most MAX_BATCH instances per wave
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
@@ -678,9 +695,14 @@ int rfde_batch_solve(rfde_batch batch, const double* const* u0, const double* co
   for (int i = 0; i < count; ++i)
     if (!u0[i] || !f[i] || !U[i]) return RFDE_EINVAL;
   RFDE_HIP(hipStreamSynchronize(batch->user));
+  if (!batch->arena.base) {
+    RFDE_HIP(hipMalloc((void**)&batch->arena.base, batch->info.wave_bytes_max));
+    batch->arena.size = batch->info.wave_bytes_max;
+  }
   hipStream_t st = nullptr;
   RFDE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   batch->info.ms_setup = batch->info.ms_factor = batch->info.ms_solve = 0.0;
+  batch->info.ms_plans = batch->info.ms_tune = 0.0;
   batch->info.graph_launches = 0;
   int rc = RFDE_OK;
   for (const auto& wv : batch->waves) {

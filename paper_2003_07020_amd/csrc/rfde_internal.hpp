@@ -56,6 +56,13 @@ struct ItemMap {
   int total() const { return start[cnt]; }
 };
 
+// Bump allocator over one device allocation (a batch keeps one for all its waves, so device
+// memory is mapped once instead of per plan and per wave).
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+};
+
 struct Plan {
   int dim = 1;
   int M = 0, Mx = 0, My = 0, S = 0;   // S = spatial unknowns per time level
@@ -73,6 +80,7 @@ struct Plan {
   // Batch member: per-instance kernels of the iteration return at once while *live == 0
   // (the instance has converged in the current restart cycle).  NULL for ordinary plans.
   const int* live = nullptr;
+  Arena* arena = nullptr;    // device buffers come from here (not freed by free_plan) if set
   // Launch-shape variants (chosen by the tuner; 0 = the built-in default):
   //   tv_time:   time FFTs with NB >> tv_time transforms per workgroup (tv_time in 0..2)
   //   tv_matvec: 0 default, 1 the other workgroup size, 2 largest FFT radix 8 instead of 16

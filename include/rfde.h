@@ -124,8 +124,9 @@ int rfde_gk(double alpha, int n, double* g, void* hip_stream);
  *   two up to 8192 or any other count up to 4096 (its time DFTs then use Bluestein's chirp-z
  *   form with a power-of-two length >= 2 N_t - 1); opts may be NULL (defaults).
  *   RFDE_SPATIAL_TAU needs M + 1 a power of two.
- * Memory: the factors take n_freq * T(T+1)/2 * 4096 complex entries (T = ceil(M/64); 16 bytes
- * each in FP64, 8 in FP32): 69.9 GB for M = 4095, N_t = 1024 in FP64.
+ * Memory: the factors take nb * T(T+1)/2 * 4096 complex entries (T = ceil(M/64); 16 bytes
+ * each in FP64, 8 in FP32; nb = n_freq, or n_freq - 1 for an even N_t, whose real blocks 0 and
+ * N_t/2 share one complex-sized block): 69.8 GB for M = 4095, N_t = 1024 in FP64.
  * Errors: EINVAL on any range violation; EUNSUPPORTED for TAU with M + 1 not a power of two;
  * ENOMEM if factors plus workspace exceed free device memory (checked before allocating);
  * EHIP on a runtime failure.  On error *plan is set to NULL.
@@ -180,7 +181,10 @@ int rfde_apply_A(rfde_plan plan, const double* v, double* y);
 int rfde_pinv_step_a(rfde_plan plan, const double* v, void* z1);
 
 /* Step (a8), preconditioner step (b): z2_n = (lambda_n I + coef T)^{-1} z1_n for every n.
- * z1, z2: [n_freq][S] c128; may alias (in place).  async. */
+ * z1, z2: [n_freq][S] c128; may alias (in place).  Exact 1D solver with an even N_t: levels 0
+ * and N_t/2 are taken as real (as step (a) produces them from real data; their imaginary parts
+ * are ignored and written as zero), since those two blocks are real and are solved as a pair
+ * in real arithmetic.  async. */
 int rfde_pinv_step_b(rfde_plan plan, const void* z1, void* z2);
 
 /* Step (a9), preconditioner step (c): extend by z2_{N_t-n} = conj(z2_n) (imaginary parts of

@@ -23,8 +23,16 @@
 //                 then the pending diagonal tile (i, i) -= (L_ij D_j) L_ij^T (a third), so the
 //                 diagonal launches, which have only one workgroup per block, do no GEMM work.
 // B_ij is generated from g, coef and lambda_n in the accumulator initialisation, so the
-// assembled matrices are never stored.  Complex products use four real MFMAs each.
+// assembled matrices are never stored.
+//
+// Real blocks: for an even N_t, lambda_0 and lambda_{N_t/2} are real, so B_0 and B_{N_t/2} are
+// real symmetric (positive definite).  Their factors share one storage block (the "dual" block,
+// stored first): the .x components hold B_0's factor and the .y components B_{N_t/2}'s, with
+// componentwise arithmetic.  A plan then has N_t/2 storage blocks instead of N_t/2 + 1, each of
+// the same size, which divides evenly over the workgroup slots of the GPU (513 blocks of work on
+// 512 slots left one block running alone at the end of every launch).
 #include <algorithm>
+#include <type_traits>
 
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"
@@ -55,15 +63,41 @@ template <> struct mma<float2> {
 
 constexpr int LDSLD = 65;  // padded leading dimension of 64x64 tiles staged in LDS
 
-// Entry (R, Cc) of B_n, padded with identity beyond M.
+// Entry (R, Cc) of B_n, padded with identity beyond M.  D (dual block): lam = (lambda_0,
+// lambda_{N_t/2}) and the entry is (B_0[R][Cc], B_{N_t/2}[R][Cc]).
+template <bool D>
 __device__ __forceinline__ double2 shifted_entry(const double* __restrict__ g, double coef,
                                                  double2 lam, int M, int R, int Cc) {
-  if (R >= M || Cc >= M) return make_double2(R == Cc ? 1.0 : 0.0, 0.0);
+  if (R >= M || Cc >= M) {
+    const double e = R == Cc ? 1.0 : 0.0;
+    return make_double2(e, D ? e : 0.0);
+  }
   const int d = R > Cc ? R - Cc : Cc - R;
-  double re = coef * g[d];
-  double im = 0.0;
-  if (d == 0) { re += lam.x; im = lam.y; }
-  return make_double2(re, im);
+  const double t = coef * g[d];
+  if constexpr (D) return make_double2(t + (d == 0 ? lam.x : 0.0), t + (d == 0 ? lam.y : 0.0));
+  return make_double2(t + (d == 0 ? lam.x : 0.0), d == 0 ? lam.y : 0.0);
+}
+
+// Products and inverses in the arithmetic of a block: complex, or componentwise (dual block).
+template <bool D, typename C> __device__ __forceinline__ C xmul(C a, C b) {
+  if constexpr (D) return cmk<C>(a.x * b.x, a.y * b.y);
+  else return cmul(a, b);
+}
+template <bool D, typename C> __device__ __forceinline__ C xinv(C d) {
+  using R = typename cplx_traits<C>::real;
+  if constexpr (D) {
+    return cmk<C>((R)1 / d.x, (R)1 / d.y);
+  } else {
+    const R den = d.x * d.x + d.y * d.y;
+    return cmk<C>(d.x / den, -d.y / den);
+  }
+}
+
+// lambda of storage block n of family fm (the dual block 0 takes lambda_0 and lambda_{N_t/2}).
+template <bool D>
+__device__ __forceinline__ double2 block_lambda(const BlockSet* __restrict__ set, int fm, int n) {
+  if constexpr (D) return make_double2(set->lambda[fm][0].x, set->lambda[fm][set->nfreq[fm] - 1].x);
+  else return set->lambda[fm][n];
 }
 
 // Logical block index so that each XCD (blocks are dealt round-robin to 8 XCDs) walks a
@@ -98,7 +132,9 @@ template <typename C> struct WaveAcc3 {
   typename mma<C>::V p1[2][2], p2[2][2], p3[2][2];
 };
 
-template <typename C>
+// Dual blocks need two real products per entry: p1 accumulates the .x (B_0) part and p2 the
+// .y (B_{N_t/2}) part; p3 is unused.
+template <typename C, bool D>
 __device__ __forceinline__ void acc3_init(WaveAcc3<C>& a, int i, int j,
                                           const double* __restrict__ g, double coef, double2 lam,
                                           int M) {
@@ -113,32 +149,51 @@ __device__ __forceinline__ void acc3_init(WaveAcc3<C>& a, int i, int j,
       for (int e = 0; e < 4; ++e) {
         const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
         const int c = wc * 32 + bj * 16 + l16;
-        const double2 b = shifted_entry(g, coef, lam, M, i * TILE + r, j * TILE + c);
+        const double2 b = shifted_entry<D>(g, coef, lam, M, i * TILE + r, j * TILE + c);
         a.p1[bi][bj][e] = (R)b.x;
-        a.p2[bi][bj][e] = (R)0;
-        a.p3[bi][bj][e] = (R)(b.x + b.y);
+        if constexpr (D) {
+          a.p2[bi][bj][e] = (R)b.y;
+        } else {
+          a.p2[bi][bj][e] = (R)0;
+          a.p3[bi][bj][e] = (R)(b.x + b.y);
+        }
       }
 }
 
-template <typename C>
+template <typename C, bool D>
 __device__ __forceinline__ void acc3_finish(const WaveAcc3<C>& a, WaveAcc<C>& acc) {
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      acc.re[bi][bj] = a.p1[bi][bj] - a.p2[bi][bj];
-      acc.im[bi][bj] = a.p3[bi][bj] - a.p1[bi][bj] - a.p2[bi][bj];
+      if constexpr (D) {
+        acc.re[bi][bj] = a.p1[bi][bj];
+        acc.im[bi][bj] = a.p2[bi][bj];
+      } else {
+        acc.re[bi][bj] = a.p1[bi][bj] - a.p2[bi][bj];
+        acc.im[bi][bj] = a.p3[bi][bj] - a.p1[bi][bj] - a.p2[bi][bj];
+      }
     }
 }
 
 // One K step of 4: A entries na (the -(L_ik d_k) values) for the wave's two row blocks, B
 // entries b (L_jk) for its two column blocks.
-template <typename C>
+template <typename C, bool D>
 __device__ __forceinline__ void acc3_step(WaveAcc3<C>& a, const typename mma<C>::R (&nar)[2],
                                           const typename mma<C>::R (&nai)[2],
                                           const typename mma<C>::R (&br)[2],
                                           const typename mma<C>::R (&bim)[2]) {
   using R = typename mma<C>::R;
+  if constexpr (D) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        a.p1[bi][bj] = mma<C>::fma(nar[bi], br[bj], a.p1[bi][bj]);
+        a.p2[bi][bj] = mma<C>::fma(nai[bi], bim[bj], a.p2[bi][bj]);
+      }
+    return;
+  }
   R sa[2], sb[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -168,7 +223,7 @@ template <typename C> struct StageBuf {
   C D[2][KC];
 };
 
-template <typename C>
+template <typename C, bool D>
 __device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __restrict__ fac,
                                                    int i, int j, const double* __restrict__ g,
                                                    double coef, double2 lam, int M,
@@ -179,10 +234,10 @@ __device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __r
   const int wr = w >> 1, wc = w & 1;
   const int l16 = lane & 15, lq = lane >> 4;
   WaveAcc3<C> a3;
-  acc3_init<C>(a3, i, j, g, coef, lam, M);
+  acc3_init<C, D>(a3, i, j, g, coef, lam, M);
   const int nchunk = j * (TILE / KC);
   if (nchunk == 0) {
-    acc3_finish<C>(a3, acc);
+    acc3_finish<C, D>(a3, acc);
     return;
   }
   // per thread: 4 entries of each operand chunk (KC*64 = 1024 = 4 x 256) and one d
@@ -222,8 +277,13 @@ __device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __r
       for (int bi = 0; bi < 2; ++bi) {
         const C a = sb.A[cur][kk * TILE + wr * 32 + bi * 16 + l16];
         // na = -(a d)
-        nar[bi] = -(a.x * d.x - a.y * d.y);
-        nai[bi] = -(a.x * d.y + a.y * d.x);
+        if constexpr (D) {
+          nar[bi] = -(a.x * d.x);
+          nai[bi] = -(a.y * d.y);
+        } else {
+          nar[bi] = -(a.x * d.x - a.y * d.y);
+          nai[bi] = -(a.x * d.y + a.y * d.x);
+        }
       }
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
@@ -231,17 +291,17 @@ __device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __r
         br[bj] = b.x;
         bim[bj] = b.y;
       }
-      acc3_step<C>(a3, nar, nai, br, bim);
+      acc3_step<C, D>(a3, nar, nai, br, bim);
     }
     if (c + 1 < nchunk) lstore(cur ^ 1);
     __syncthreads();
   }
-  acc3_finish<C>(a3, acc);
+  acc3_finish<C, D>(a3, acc);
 }
 
 // acc = B_ij - sum_{k<j} (L_ik D_k) L_jk^T, operands read by each wave straight from global
 // memory in the MFMA lane layout (used for FP64, whose MFMAs are slow enough to hide the loads).
-template <typename C>
+template <typename C, bool D>
 __device__ __forceinline__ void tile_update_direct(WaveAcc<C>& acc, const C* __restrict__ fac, int i,
                                             int j, const double* __restrict__ g, double coef,
                                             double2 lam, int M) {
@@ -250,7 +310,7 @@ __device__ __forceinline__ void tile_update_direct(WaveAcc<C>& acc, const C* __r
   const int wr = w >> 1, wc = w & 1;
   const int l16 = lane & 15, lq = lane >> 4;
   WaveAcc3<C> a3;
-  acc3_init<C>(a3, i, j, g, coef, lam, M);
+  acc3_init<C, D>(a3, i, j, g, coef, lam, M);
   for (int k = 0; k < j; ++k) {
     const C* Lik = fac + tile_index(i, k) * TILE_ELEMS;
     const C* Ljk = fac + tile_index(j, k) * TILE_ELEMS;
@@ -264,8 +324,13 @@ __device__ __forceinline__ void tile_update_direct(WaveAcc<C>& acc, const C* __r
       for (int bi = 0; bi < 2; ++bi) {
         const C a = Lik[kk * TILE + wr * 32 + bi * 16 + l16];
         // na = -(a d)
-        nar[bi] = -(a.x * d.x - a.y * d.y);
-        nai[bi] = -(a.x * d.y + a.y * d.x);
+        if constexpr (D) {
+          nar[bi] = -(a.x * d.x);
+          nai[bi] = -(a.y * d.y);
+        } else {
+          nar[bi] = -(a.x * d.x - a.y * d.y);
+          nai[bi] = -(a.x * d.y + a.y * d.x);
+        }
       }
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
@@ -273,10 +338,10 @@ __device__ __forceinline__ void tile_update_direct(WaveAcc<C>& acc, const C* __r
         br[bj] = b.x;
         bim[bj] = b.y;
       }
-      acc3_step<C>(a3, nar, nai, br, bim);
+      acc3_step<C, D>(a3, nar, nai, br, bim);
     }
   }
-  acc3_finish<C>(a3, acc);
+  acc3_finish<C, D>(a3, acc);
 }
 
 // Write the wave accumulators into an LDS tile (column-major, leading dimension LDSLD).
@@ -309,10 +374,8 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(const BlockSet* __restrict__ 
                                                    int j) {
   using R = typename mma<C>::R;
   __shared__ C S[TILE * LDSLD];
-  auto body = [&](int item) {
-  const int slot = find_slot(map, item);
-  const int fm = map.fam[slot];
-  const int n = item - map.start[slot];
+  auto body = [&](int slot, int fm, int n, auto dtag) {
+  constexpr bool D = decltype(dtag)::value;
   const int M = set->M[fm];
   const double* __restrict__ g = set->g[fm];
   const double coef = set->coef[fm];
@@ -320,10 +383,10 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(const BlockSet* __restrict__ 
   C* Djj = fac + tile_index(j, j) * TILE_ELEMS;
   const int t = threadIdx.x;
   if (j == 0) {
-    const double2 lam = set->lambda[fm][n];
+    const double2 lam = block_lambda<D>(set, fm, n);
     for (int e = t; e < TILE_ELEMS; e += 256) {
       const int c = e >> 6, r = e & 63;
-      const double2 b = shifted_entry(g, coef, lam, M, r, c);
+      const double2 b = shifted_entry<D>(g, coef, lam, M, r, c);
       S[c * LDSLD + r] = cmk<C>((R)b.x, (R)b.y);
     }
   } else {
@@ -333,19 +396,17 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(const BlockSet* __restrict__ 
   const int r = t & 63, cg = t >> 6;
   // column p: d = S[p][p]; S[r][c] -= S[r][p] S[c][p] / d for r >= c > p; S[r][p] /= d, r > p.
   for (int p = 0; p < TILE; ++p) {
-    const C d = S[p * LDSLD + p];
-    const R den = d.x * d.x + d.y * d.y;
-    const C dinv = cmk<C>(d.x / den, -d.y / den);
+    const C dinv = xinv<D>(S[p * LDSLD + p]);
     if (r > p) {
       const C ur = S[p * LDSLD + r];
-      const C lr = cmul(ur, dinv);
+      const C lr = xmul<D>(ur, dinv);
       for (int c = p + 1 + cg; c <= r; c += 4) {
         const C uc = S[p * LDSLD + c];
-        S[c * LDSLD + r] = csub(S[c * LDSLD + r], cmul(lr, uc));
+        S[c * LDSLD + r] = csub(S[c * LDSLD + r], xmul<D>(lr, uc));
       }
     }
     __syncthreads();
-    if (cg == 0 && r > p) S[p * LDSLD + r] = cmul(S[p * LDSLD + r], dinv);
+    if (cg == 0 && r > p) S[p * LDSLD + r] = xmul<D>(S[p * LDSLD + r], dinv);
     __syncthreads();
   }
   // x = L^{-1} e_c: x_c = 1, x_rr = -(L[rr][c] + sum_{c<m<rr} L[rr][m] x_m); L[rr][m] lives at
@@ -354,7 +415,7 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(const BlockSet* __restrict__ 
     const int c = t;
     for (int rr = c + 1; rr < TILE; ++rr) {
       C s = S[c * LDSLD + rr];
-      for (int m = c + 1; m < rr; ++m) s = cadd(s, cmul(S[m * LDSLD + rr], S[m * LDSLD + c]));
+      for (int m = c + 1; m < rr; ++m) s = cadd(s, xmul<D>(S[m * LDSLD + rr], S[m * LDSLD + c]));
       S[rr * LDSLD + c] = cmk<C>(-s.x, -s.y);
     }
   }
@@ -362,10 +423,17 @@ __global__ void __launch_bounds__(256) k_ldlt_diag(const BlockSet* __restrict__ 
   for (int e = t; e < TILE_ELEMS; e += 256) Djj[e] = S[(e & 63) * LDSLD + (e >> 6)];
   __syncthreads();  // S is reused by the next item
   };
+  auto run = [&](int item) {
+    const int slot = find_slot(map, item);
+    const int fm = map.fam[slot];
+    const int n = item - map.start[slot];
+    if (n == 0 && set->dual[fm]) body(slot, fm, n, std::true_type{});
+    else body(slot, fm, n, std::false_type{});
+  };
   if constexpr (P) {
-    for (int item = blockIdx.x; item < map.start[map.cnt]; item += gridDim.x) body(item);
+    for (int item = blockIdx.x; item < map.start[map.cnt]; item += gridDim.x) run(item);
   } else {
-    body(blockIdx.x);
+    run(blockIdx.x);
   }
 }
 
@@ -381,24 +449,20 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
   __shared__ __align__(16) unsigned char smem[SB > ST ? SB : ST];
   StageBuf<C>& sb = *reinterpret_cast<StageBuf<C>*>(smem);
   C* S = reinterpret_cast<C*>(smem);
-  auto body = [&](int item) {
-  const int slot = find_slot(map, item);
-  const int fm = map.fam[slot];
+  auto body = [&](int slot, int fm, int n, int i, auto dtag) {
+  constexpr bool D = decltype(dtag)::value;
   const int T = set->T[fm], M = set->M[fm];
   const double* __restrict__ g = set->g[fm];
   const double coef = set->coef[fm];
-  const int per = T - 1 - j;
-  const int lb = item - map.start[slot];
-  const int n = lb / per, i = j + 1 + lb % per;
-  const double2 lamn = set->lambda[fm][n];
+  const double2 lamn = block_lambda<D>(set, fm, n);
   C* fac = (C*)map.fac[slot] + (size_t)n * lower_tiles(T) * TILE_ELEMS;
   {
     WaveAcc<C> acc;
     if constexpr (sizeof(C) == 8) {
-      tile_update_staged<C>(acc, fac, i, j, g, coef, lamn, M, sb);
+      tile_update_staged<C, D>(acc, fac, i, j, g, coef, lamn, M, sb);
       __syncthreads();  // staging buffers are reused as S
     } else {
-      tile_update_direct<C>(acc, fac, i, j, g, coef, lamn, M);
+      tile_update_direct<C, D>(acc, fac, i, j, g, coef, lamn, M);
     }
     acc_to_lds<C>(acc, S);
   }
@@ -429,7 +493,7 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
       const int c = wc * 32 + bj * 16 + l16;
       C b;
       if (c > m) b = Djj[m * TILE + c];
-      else b = cmk<C>((R)(c == m ? 1 : 0), (R)0);
+      else b = cmk<C>((R)(c == m ? 1 : 0), (R)(D && c == m ? 1 : 0));
       br[bj] = b.x; bim[bj] = b.y;
     }
 #pragma unroll
@@ -437,9 +501,13 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
         x.re[bi][bj] = mma<C>::fma(sr[bi], br[bj], x.re[bi][bj]);
-        x.re[bi][bj] = mma<C>::fma(nsi[bi], bim[bj], x.re[bi][bj]);
-        x.im[bi][bj] = mma<C>::fma(sr[bi], bim[bj], x.im[bi][bj]);
-        x.im[bi][bj] = mma<C>::fma(si[bi], br[bj], x.im[bi][bj]);
+        if constexpr (D) {
+          x.im[bi][bj] = mma<C>::fma(si[bi], bim[bj], x.im[bi][bj]);
+        } else {
+          x.re[bi][bj] = mma<C>::fma(nsi[bi], bim[bj], x.re[bi][bj]);
+          x.im[bi][bj] = mma<C>::fma(sr[bi], bim[bj], x.im[bi][bj]);
+          x.im[bi][bj] = mma<C>::fma(si[bi], br[bj], x.im[bi][bj]);
+        }
       }
   }
   __syncthreads();  // everyone is done reading S
@@ -449,13 +517,11 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
       const int c = wc * 32 + bj * 16 + l16;
-      const C d = Djj[c * (TILE + 1)];
-      const R den = d.x * d.x + d.y * d.y;
-      const C dinv = cmk<C>(d.x / den, -d.y / den);
+      const C dinv = xinv<D>(Djj[c * (TILE + 1)]);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = wr * 32 + bi * 16 + mma<C>::row(lane, e);
-        S[c * LDSLD + r] = cmul(cmk<C>(x.re[bi][bj][e], x.im[bi][bj][e]), dinv);
+        S[c * LDSLD + r] = xmul<D>(cmk<C>(x.re[bi][bj][e], x.im[bi][bj][e]), dinv);
       }
     }
   __syncthreads();
@@ -480,7 +546,7 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
       R ar[2], ai[2], nai[2], br[2], bim[2];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
-        const C a = cmul(S[m * LDSLD + wr * 32 + bi * 16 + l16], d);
+        const C a = xmul<D>(S[m * LDSLD + wr * 32 + bi * 16 + l16], d);
         ar[bi] = a.x; ai[bi] = a.y; nai[bi] = -a.y;
       }
 #pragma unroll
@@ -493,9 +559,13 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
           dl.re[bi][bj] = mma<C>::fma(ar[bi], br[bj], dl.re[bi][bj]);
-          dl.re[bi][bj] = mma<C>::fma(nai[bi], bim[bj], dl.re[bi][bj]);
-          dl.im[bi][bj] = mma<C>::fma(ar[bi], bim[bj], dl.im[bi][bj]);
-          dl.im[bi][bj] = mma<C>::fma(ai[bi], br[bj], dl.im[bi][bj]);
+          if constexpr (D) {
+            dl.im[bi][bj] = mma<C>::fma(ai[bi], bim[bj], dl.im[bi][bj]);
+          } else {
+            dl.re[bi][bj] = mma<C>::fma(nai[bi], bim[bj], dl.re[bi][bj]);
+            dl.im[bi][bj] = mma<C>::fma(ar[bi], bim[bj], dl.im[bi][bj]);
+            dl.im[bi][bj] = mma<C>::fma(ai[bi], br[bj], dl.im[bi][bj]);
+          }
         }
     }
   }
@@ -504,7 +574,7 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
   if (j == 0) {
     for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) {
       const int c = e >> 6, r = e & 63;
-      const double2 b = shifted_entry(g, coef, lamn, M, i * TILE + r, i * TILE + c);
+      const double2 b = shifted_entry<D>(g, coef, lamn, M, i * TILE + r, i * TILE + c);
       S[c * LDSLD + r] = cmk<C>((R)b.x, (R)b.y);
     }
   } else {
@@ -527,16 +597,25 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
   for (int e = threadIdx.x; e < TILE_ELEMS; e += 256) Pii[e] = S[(e >> 6) * LDSLD + (e & 63)];
   __syncthreads();  // smem is reused by the next item
   };
+  auto run = [&](int item) {
+    const int slot = find_slot(map, item);
+    const int fm = map.fam[slot];
+    const int per = set->T[fm] - 1 - j;
+    const int lb = item - map.start[slot];
+    const int n = lb / per, i = j + 1 + lb % per;
+    if (n == 0 && set->dual[fm]) body(slot, fm, n, i, std::true_type{});
+    else body(slot, fm, n, i, std::false_type{});
+  };
   const int lbr = xcd_remap(blockIdx.x, gridDim.x);
   if constexpr (P) {
     const int total = map.start[map.cnt];
-    for (int base = 0; base + lbr < total; base += gridDim.x) body(base + lbr);
+    for (int base = 0; base + lbr < total; base += gridDim.x) run(base + lbr);
   } else {
-    body(lbr);
+    run(lbr);
   }
 }
 
-// Items of column j: diag -> nf per family with T > j; panel -> nf (T - 1 - j) per family.
+// Items of column j: diag -> nb per family with T > j; panel -> nb (T - 1 - j) per family.
 static ItemMap column_map(const BlockSet& hs, int j, bool panel) {
   ItemMap m;
   m.cnt = 0;
@@ -546,7 +625,7 @@ static ItemMap column_map(const BlockSet& hs, int j, bool panel) {
     if (per <= 0) continue;
     m.fam[m.cnt] = k;
     m.fac[m.cnt] = hs.fac[k];
-    m.start[m.cnt + 1] = m.start[m.cnt] + hs.nf[k] * per;
+    m.start[m.cnt + 1] = m.start[m.cnt] + hs.nb[k] * per;
     ++m.cnt;
   }
   return m;
@@ -587,9 +666,7 @@ int launch_factorize_set(const BlockSet& hs, const BlockSet* ds, int bits, int g
 static BlockSet plan_set(const Plan& p) {
   BlockSet hs{};
   hs.count = 1;
-  hs.nf[0] = p.nf; hs.M[0] = p.M; hs.T[0] = p.T;
-  hs.fac[0] = p.factors; hs.g[0] = p.g; hs.lambda[0] = p.lambda; hs.coef[0] = p.coef;
-  hs.live[0] = p.live;
+  set_family(hs, 0, p);
   return hs;
 }
 
@@ -625,18 +702,23 @@ __global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, 
   __shared__ C xs[TMAX * TILE];
   __shared__ C red[4][TILE];
   __shared__ C tb[TILE];
-  auto body = [&](int item) {
-  const int slot = find_slot(map, item);
-  const int fm = map.fam[slot];
-  if (set->live[fm] && *set->live[fm] == 0) return;  // uniform across the workgroup
-  const int n = item - map.start[slot];
+  auto body = [&](int slot, int fm, int n, auto dtag) {
+  constexpr bool D = decltype(dtag)::value;
   const int M = set->M[fm], T = set->T[fm];
   const C* fac = (const C*)map.fac[slot] + (size_t)n * lower_tiles(T) * TILE_ELEMS;
   const C* zin = (const C*)io.in[fm];
   C* zout = (C*)io.out[fm];
+  const size_t nyq = (size_t)(set->nfreq[fm] - 1) * M;  // dual block: level N_t/2 of z
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int Mp = T * TILE;
-  for (int r = t; r < Mp; r += 256) xs[r] = (r < M) ? zin[(size_t)n * M + r] : cmk<C>((R)0, (R)0);
+  for (int r = t; r < Mp; r += 256) {
+    C v = cmk<C>((R)0, (R)0);
+    if (r < M) {
+      if constexpr (D) v = cmk<C>(zin[r].x, zin[nyq + r].x);  // both right-hand sides are real
+      else v = zin[(size_t)n * M + r];
+    }
+    xs[r] = v;
+  }
   __syncthreads();
   // forward.  The off-diagonal tiles of tile row i are contiguous (tile index i(i+1)/2 + k), so
   // two consecutive tiles are fetched together to keep 32 loads per lane in flight.
@@ -654,14 +736,14 @@ __global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, 
       }
 #pragma unroll
       for (int cc = 0; cc < 16; ++cc) {
-        acc = cadd(acc, cmul(a0[cc], xs[k * TILE + 16 * w + cc]));
-        acc1 = cadd(acc1, cmul(a1[cc], xs[(k + 1) * TILE + 16 * w + cc]));
+        acc = cadd(acc, xmul<D>(a0[cc], xs[k * TILE + 16 * w + cc]));
+        acc1 = cadd(acc1, xmul<D>(a1[cc], xs[(k + 1) * TILE + 16 * w + cc]));
       }
     }
     if (k < i) {
       const C* L0 = Lrow + (size_t)k * TILE_ELEMS;
 #pragma unroll
-      for (int cc = 0; cc < 16; ++cc) acc = cadd(acc, cmul(L0[cc * TILE], xs[k * TILE + 16 * w + cc]));
+      for (int cc = 0; cc < 16; ++cc) acc = cadd(acc, xmul<D>(L0[cc * TILE], xs[k * TILE + 16 * w + cc]));
     }
     acc = cadd(acc, acc1);
     red[w][lane] = acc;
@@ -676,7 +758,7 @@ __global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, 
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
       const int c = 16 * w + cc;
-      if (lane > c) acc2 = cadd(acc2, cmul(Dii[c * TILE + lane], tb[c]));
+      if (lane > c) acc2 = cadd(acc2, xmul<D>(Dii[c * TILE + lane], tb[c]));
     }
     red[w][lane] = acc2;
     __syncthreads();
@@ -689,9 +771,7 @@ __global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, 
   // diagonal
   for (int r = t; r < Mp; r += 256) {
     const C* Dkk = fac + tile_index(r >> 6, r >> 6) * TILE_ELEMS;
-    const C d = Dkk[(r & 63) * (TILE + 1)];
-    const R den = d.x * d.x + d.y * d.y;
-    xs[r] = cmul(xs[r], cmk<C>(d.x / den, -d.y / den));
+    xs[r] = xmul<D>(xs[r], xinv<D>(Dkk[(r & 63) * (TILE + 1)]));
   }
   __syncthreads();
   // backward
@@ -711,13 +791,14 @@ __global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, 
       }
       const C x0 = xs[i * TILE + lane], x1 = xs[(i + 1) * TILE + lane];
 #pragma unroll
-      for (int cc = 0; cc < 16; ++cc) acc[cc] = cadd(acc[cc], cadd(cmul(a0[cc], x0), cmul(a1[cc], x1)));
+      for (int cc = 0; cc < 16; ++cc)
+        acc[cc] = cadd(acc[cc], cadd(xmul<D>(a0[cc], x0), xmul<D>(a1[cc], x1)));
     }
     if (i < T) {
       const C* L0 = fac + tile_index(i, k) * TILE_ELEMS + (16 * w) * TILE + lane;
       const C x0 = xs[i * TILE + lane];
 #pragma unroll
-      for (int cc = 0; cc < 16; ++cc) acc[cc] = cadd(acc[cc], cmul(L0[cc * TILE], x0));
+      for (int cc = 0; cc < 16; ++cc) acc[cc] = cadd(acc[cc], xmul<D>(L0[cc * TILE], x0));
     }
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
@@ -731,7 +812,7 @@ __global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, 
     for (int cc = 0; cc < 16; ++cc) {
       const int c = 16 * w + cc;
       C pterm = cmk<C>((R)0, (R)0);
-      if (lane > c) pterm = cmul(Dkk[c * TILE + lane], tr);
+      if (lane > c) pterm = xmul<D>(Dkk[c * TILE + lane], tr);
       else if (lane == c) pterm = tr;
       acc[cc] = wave_sum(pterm);
     }
@@ -740,13 +821,28 @@ __global__ void __launch_bounds__(256) k_trsv(const BlockSet* __restrict__ set, 
       if (lane == cc) xs[k * TILE + 16 * w + cc] = acc[cc];
     __syncthreads();
   }
-  for (int r = t; r < M; r += 256) zout[(size_t)n * M + r] = xs[r];
+  for (int r = t; r < M; r += 256) {
+    if constexpr (D) {
+      zout[r] = cmk<C>(xs[r].x, (R)0);
+      zout[nyq + r] = cmk<C>(xs[r].y, (R)0);
+    } else {
+      zout[(size_t)n * M + r] = xs[r];
+    }
+  }
   __syncthreads();  // xs is reused by the next item
   };
+  auto run = [&](int item) {
+    const int slot = find_slot(map, item);
+    const int fm = map.fam[slot];
+    if (set->live[fm] && *set->live[fm] == 0) return;  // uniform across the workgroup
+    const int n = item - map.start[slot];
+    if (n == 0 && set->dual[fm]) body(slot, fm, n, std::true_type{});
+    else body(slot, fm, n, std::false_type{});
+  };
   if constexpr (P) {
-    for (int item = blockIdx.x; item < map.start[map.cnt]; item += gridDim.x) body(item);
+    for (int item = blockIdx.x; item < map.start[map.cnt]; item += gridDim.x) run(item);
   } else {
-    body(blockIdx.x);
+    run(blockIdx.x);
   }
 }
 
@@ -764,7 +860,7 @@ int launch_trsv_set(const BlockSet& hs, const BlockSet* ds, const void* const* z
     if (!zin[k] || !zout[k]) continue;  // family skipped in this launch
     m.fam[m.cnt] = k;
     m.fac[m.cnt] = hs.fac[k];
-    m.start[m.cnt + 1] = m.start[m.cnt] + hs.nf[k];
+    m.start[m.cnt + 1] = m.start[m.cnt] + hs.nb[k];
     ++m.cnt;
   }
   if (m.total() == 0) return RFDE_OK;
@@ -786,9 +882,10 @@ int launch_trsv(const Plan& p, const void* zin, void* zout) {
   return launch_trsv_set(hs, p.set, &zin, &zout, p.opts.precond_bits, p.trsv_cap, p.stream);
 }
 
-// Export block `index` as a dense row-major Mp x Mp matrix: strict lower = L, diagonal = D.
+// Export frequency block `index` as a dense row-major Mp x Mp matrix: strict lower = L,
+// diagonal = D.  comp < 0: a complex block; comp = 0 / 1: the .x / .y part of the dual block.
 template <typename C>
-__global__ void k_export_factor(const C* __restrict__ fac, C* __restrict__ out, int T) {
+__global__ void k_export_factor(const C* __restrict__ fac, C* __restrict__ out, int T, int comp) {
   const int Mp = T * TILE;
   const size_t total = (size_t)Mp * Mp;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
@@ -800,6 +897,10 @@ __global__ void k_export_factor(const C* __restrict__ fac, C* __restrict__ out, 
     if (i > j) val = fac[tile_index(i, j) * TILE_ELEMS + c * TILE + r];
     else if (i == j && r > c) val = fac[tile_index(i, i) * TILE_ELEMS + r * TILE + c];  // L^T store
     else if (i == j && r == c) val = fac[tile_index(i, i) * TILE_ELEMS + c * (TILE + 1)];
+    if (comp >= 0) {
+      val.x = comp == 0 ? val.x : val.y;
+      val.y = 0;
+    }
     out[e] = val;
   }
 }
@@ -808,12 +909,18 @@ int launch_export_factor(const Plan& p, int index, void* dst) {
   const size_t sys = lower_tiles(p.T) * TILE_ELEMS;
   const size_t total = (size_t)p.Mp * p.Mp;
   const int blocks = (int)std::min<size_t>((total + 255) / 256, 16384);
+  // frequency -> storage block (the dual block 0 holds frequencies 0 and N_t/2)
+  int blk = index, comp = -1;
+  if (p.dual) {
+    if (index == 0) comp = 0;
+    else if (index == p.nf - 1) { blk = 0; comp = 1; }
+  }
   if (p.opts.precond_bits == 32)
-    k_export_factor<float2><<<blocks, 256, 0, p.stream>>>((const float2*)p.factors + index * sys,
-                                                          (float2*)dst, p.T);
+    k_export_factor<float2><<<blocks, 256, 0, p.stream>>>((const float2*)p.factors + blk * sys,
+                                                          (float2*)dst, p.T, comp);
   else
-    k_export_factor<double2><<<blocks, 256, 0, p.stream>>>((const double2*)p.factors + index * sys,
-                                                           (double2*)dst, p.T);
+    k_export_factor<double2><<<blocks, 256, 0, p.stream>>>((const double2*)p.factors + blk * sys,
+                                                           (double2*)dst, p.T, comp);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

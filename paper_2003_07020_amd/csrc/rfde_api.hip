@@ -123,8 +123,7 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
     RFDE_TRY(palloc(p, &p->factors, p->factor_bytes));
     BlockSet hs{};
     hs.count = 1;
-    hs.nf[0] = p->nf; hs.M[0] = p->M; hs.T[0] = p->T;
-    hs.fac[0] = p->factors; hs.g[0] = p->g; hs.lambda[0] = p->lambda; hs.coef[0] = p->coef;
+    set_family(hs, 0, *p);
     RFDE_TRY(dalloc(p, &p->set, 1, &ws));
     p->workspace_bytes = ws;
     RFDE_HIP(hipMemcpy(p->set, &hs, sizeof(BlockSet), hipMemcpyHostToDevice));
@@ -221,8 +220,10 @@ int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M,
   if (o.spatial == RFDE_SPATIAL_EXACT) {
     p->T = (M + TILE - 1) / TILE;
     p->Mp = p->T * TILE;
+    p->dual = (Nt % 2) == 0;
+    p->nb = p->nf - (p->dual ? 1 : 0);
     const size_t csz = o.precond_bits == 32 ? 8 : 16;
-    p->factor_bytes = (size_t)p->nf * lower_tiles(p->T) * TILE_ELEMS * csz;
+    p->factor_bytes = (size_t)p->nb * lower_tiles(p->T) * TILE_ELEMS * csz;
   }
   return RFDE_OK;
 }

@@ -427,9 +427,7 @@ int solve_wave(rfde_batch_& B, const std::vector<int>& idx, const double* const*
     hS->x[k] = p.xvec;
     hS->F[k] = p.Fvec;
     hS->live[k] = 1;
-    hs.nf[k] = p.nf; hs.M[k] = p.M; hs.T[k] = p.T;
-    hs.fac[k] = p.factors; hs.g[k] = p.g; hs.lambda[k] = p.lambda; hs.coef[k] = p.coef;
-    hs.live[k] = p.live;
+    set_family(hs, k, p);
   }
   RFDE_HIP(hipMemcpy(w.S, hS, sizeof(WaveState), hipMemcpyHostToDevice));
   RFDE_HIP(hipMemcpy(w.ds, &hs, sizeof(BlockSet), hipMemcpyHostToDevice));

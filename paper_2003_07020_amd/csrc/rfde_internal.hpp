@@ -34,7 +34,9 @@ __host__ __device__ inline size_t tile_index(int i, int j) { return (size_t)i * 
 constexpr int MAX_BATCH = 64;
 struct BlockSet {
   int count;
-  int nf[MAX_BATCH];                 // blocks (frequencies) of family k
+  int nb[MAX_BATCH];                 // storage blocks of family k (work items per tile)
+  int nfreq[MAX_BATCH];              // frequencies floor(N_t/2)+1 (rows of its z arrays)
+  int dual[MAX_BATCH];               // 1: storage block 0 holds the real blocks 0 and N_t/2
   int M[MAX_BATCH];                  // order
   int T[MAX_BATCH];                  // tile count, ceil(M / 64)
   void* fac[MAX_BATCH];              // nf x lower_tiles(T) x 4096 complex
@@ -70,6 +72,8 @@ struct Plan {
   int Lt = 0;                         // time transform length: Nt, or the Bluestein length
   int L = 0, Lx = 0, Ly = 0;
   int Mp = 0, T = 0;                  // padded order and tile count of the factored blocks
+  int nb = 0;                         // storage blocks of the factors (nf, or nf - 1 if dual)
+  bool dual = false;                  // even N_t: blocks 0 and N_t/2 (real) share storage block 0
   double alpha = 0, alpha_x = 0, alpha_y = 0;
   double kappa = 0, kappa_x = 0, kappa_y = 0;
   double h = 0, hx = 0, hy = 0, tau = 0, eps = 0;
@@ -122,6 +126,20 @@ struct Plan {
 
   size_t N() const { return (size_t)Nt * S; }
 };
+
+// Family k of a block set = the factor blocks of plan p.
+inline void set_family(BlockSet& hs, int k, const Plan& p) {
+  hs.nb[k] = p.nb;
+  hs.nfreq[k] = p.nf;
+  hs.dual[k] = p.dual ? 1 : 0;
+  hs.M[k] = p.M;
+  hs.T[k] = p.T;
+  hs.fac[k] = p.factors;
+  hs.g[k] = p.g;
+  hs.lambda[k] = p.lambda;
+  hs.coef[k] = p.coef;
+  hs.live[k] = p.live;
+}
 
 // ---- plan life cycle (rfde_api.hip) ----
 int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M, int Nt,

@@ -143,7 +143,7 @@ int tune_plan(Plan& p, int what, rfde_tune_report* rep) {
   best = p.trsv_cap;
   const size_t csz = p.opts.precond_bits == 32 ? 8 : 16;
   if ((what & 4) && p.factor_bytes && (size_t)p.nf * p.S * csz <= (size_t)p.opts.restart * N * sizeof(double)) {
-    const std::string ks = key_of("trsv", p, p.T, p.nf);
+    const std::string ks = key_of("trsv", p, p.T, p.nb);
     if (lookup(ks, &best)) {
       r.from_cache |= 4;
     } else {
@@ -151,7 +151,7 @@ int tune_plan(Plan& p, int what, rfde_tune_report* rep) {
       double bms = 1e300;
       for (int c = 0; c < 5; ++c) {
         r.trsv_caps[c] = caps[c];
-        if (caps[c] != 0 && caps[c] >= p.nf) { r.ms_trsv[c] = -1.0; continue; }
+        if (caps[c] != 0 && caps[c] >= p.nb) { r.ms_trsv[c] = -1.0; continue; }
         p.trsv_cap = caps[c];
         double ms = 0;
         RFDE_TRY(time_ms(p, [&]() -> int { return launch_trsv(p, p.zf, p.zbuf); }, 2, &ms));

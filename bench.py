@@ -156,14 +156,19 @@ def measure_form(bits, args, W, alphas, inputs, dev, spatial="exact"):
 
     fp32 = bits == 32
     nf = info["n_freq"]
-    flops_factor = nf * (4.0 / 3.0) * float(M) ** 3
+    # complex blocks: (4/3) M^3 real flops each (LDL^T, M^3/6 complex multiply-adds); for an
+    # even N_t the blocks 0 and N_t/2 are real: (1/3) M^3 each
+    n_real = 2 if Nt % 2 == 0 else 1
+    flops_factor = ((nf - n_real) * (4.0 / 3.0) + n_real / 3.0) * float(M) ** 3
     ms_factor = float(np.mean([r["ms_factor"] for r in recs]))
     achieved = flops_factor / (ms_factor * 1e-3) / 1e12 if ms_factor > 0 else None
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     esz = 8 if fp32 else 16
-    # exact: the LDL^T factors are streamed (16 M^2 bytes per block for complex128);
-    # tau: the half spectrum is read and written by the DST solves (2 x 16 B per entry)
-    bytes_b = nf * float(M) * M * esz if spatial == "exact" else 2.0 * nf * M * 16
+    # exact: the LDL^T factors are streamed twice (forward and backward): M^2 entries of esz
+    # bytes per complex block, half that per real block; tau: the half spectrum is read and
+    # written by the DST solves (2 x 16 B per entry)
+    bytes_b = ((nf - n_real) + 0.5 * n_real) * float(M) * M * esz if spatial == "exact" \
+        else 2.0 * nf * M * 16
     # step (b) is timed through the C ABI; for FP32 plans that call also converts c128 <-> c64
     # around the solves (about 0.1% of its bytes at this size).
     N = float(Nt) * M
@@ -291,7 +296,11 @@ def measure_batched(args, dev):
     ms_batch = (time.perf_counter() - t0) * 1e3
     info = b.info
     b.destroy()
-    flops = sum((d["Nt"] // 2 + 1) * (4.0 / 3.0) * float(d["M"]) ** 3 for d in inst)
+    def factor_flops(M, Nt):
+        nf, n_real = Nt // 2 + 1, (2 if Nt % 2 == 0 else 1)
+        return ((nf - n_real) * (4.0 / 3.0) + n_real / 3.0) * float(M) ** 3
+
+    flops = sum(factor_flops(d["M"], d["Nt"]) for d in inst)
 
     def one_by_one(bits):
         U = torch.empty(max(d["M"] * d["Nt"] for d in inst), dtype=torch.float64, device=dev)
@@ -399,8 +408,12 @@ def main():
     forms = [f for f in forms if f not in ("learned", "batched")]
     # fp64: the plain exact-LDL^T form; fp32: its FP32 preconditioner; tau: the paper's own step
     # (b) (DST-I diagonalisation of the tau approximation, no factors), FP64
+    from paper_2003_07020_amd.rfde import release_cached_memory
     results = {}
     for f in forms:
+        # each form starts from unmapped device memory; its warm-up step maps what the timed
+        # steps then reuse (the library caches freed device blocks)
+        release_cached_memory()
         results[f] = measure_form(32 if f == "fp32" else 64, args, W, alphas, inputs, dev,
                                   spatial="tau" if f == "tau" else "exact")
         progress(f"form {f} done")

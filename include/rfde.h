@@ -144,8 +144,14 @@ int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double 
                         double kappa_y, double ax, double bx, double ay, double by, int Mx, int My,
                         int Nt, double T, const rfde_opts* opts, void* hip_stream);
 
-/* Release every device buffer the plan owns.  Accepts NULL. */
+/* Release every device buffer the plan owns (to the library's device-memory cache: mapping
+ * fresh device memory costs ~10-20 ms per GB, so freed blocks are reused by later plans and
+ * batches; see rfde_release_cached_memory).  Accepts NULL. */
 int rfde_plan_destroy(rfde_plan plan);
+
+/* Return every cached device block to the HIP runtime (hipFree); returns the bytes released.
+ * A failed allocation inside the library does this by itself before giving up. */
+size_t rfde_release_cached_memory(void);
 
 /* Sizes and derived parameters of a plan (host struct). */
 int rfde_plan_get_info(rfde_plan plan, rfde_plan_info* info);
@@ -211,12 +217,14 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
  * work split differs.
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
-  int time_variant;      /* time FFTs: NB >> v transforms per workgroup, v in 0..2            */
-  int matvec_variant;    /* 0 default; 1 other workgroup size; 2 largest FFT radix 8          */
+  int time_variant;      /* time FFTs: NB >> v transforms per workgroup (v = 0..2), or 3: NB
+                            with 1024 threads and radix-8 passes (power-of-two N_t only)     */
+  int matvec_variant;    /* 0 default; 1 other workgroup size; 2 largest FFT radix 8;
+                            3 1024 threads with radix 8                                        */
   int trsv_grid_cap;     /* 0 one workgroup per block; else persistent workgroups             */
   int from_cache;        /* bit 0 time, bit 1 matvec, bit 2 trsv: taken from the cache        */
-  double ms_time[3];     /* timed forward + inverse time FFT per variant (0 when cached)      */
-  double ms_matvec[3];   /* timed matvec per variant                                           */
+  double ms_time[4];     /* timed forward + inverse time FFT per variant (0 when cached)      */
+  double ms_matvec[4];   /* timed matvec per variant                                           */
   int trsv_caps[5];      /* candidate caps                                                      */
   double ms_trsv[5];     /* timed triangular solves per cap (-1: not applicable)               */
 } rfde_tune_report;
@@ -230,7 +238,7 @@ typedef struct {
  */
 int rfde_plan_autotune(rfde_plan plan, rfde_tune_report* report);
 
-/* Set the variants directly (time_variant 0..2, matvec_variant 0..2, trsv_grid_cap >= 0). */
+/* Set the variants directly (time_variant 0..3, matvec_variant 0..3, trsv_grid_cap >= 0). */
 int rfde_plan_set_variants(rfde_plan plan, int time_variant, int matvec_variant,
                            int trsv_grid_cap);
 

@@ -62,7 +62,7 @@ class BatchInfo(C.Structure):
 class TuneReport(C.Structure):
     _fields_ = [("time_variant", C.c_int), ("matvec_variant", C.c_int),
                 ("trsv_grid_cap", C.c_int), ("from_cache", C.c_int),
-                ("ms_time", C.c_double * 3), ("ms_matvec", C.c_double * 3),
+                ("ms_time", C.c_double * 4), ("ms_matvec", C.c_double * 4),
                 ("trsv_caps", C.c_int * 5), ("ms_trsv", C.c_double * 5)]
 
 
@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
     L.rfde_apply_Pinv.argtypes = [vp, vp, vp]
     L.rfde_solve.argtypes = [vp, vp, vp, vp, vp, d, C.POINTER(Stats)]
     L.rfde_plan_autotune.argtypes = [vp, C.POINTER(TuneReport)]
+    L.rfde_release_cached_memory.argtypes = []
+    L.rfde_release_cached_memory.restype = C.c_size_t
     L.rfde_plan_set_variants.argtypes = [vp, i, i, i]
     L.rfde_batch_create.argtypes = [C.POINTER(vp), i, C.POINTER(Instance), C.POINTER(Opts),
                                     C.c_size_t, vp]

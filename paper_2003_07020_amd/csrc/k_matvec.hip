@@ -118,12 +118,13 @@ __global__ void __launch_bounds__(NT) k_matvec_2d_y(const double* __restrict__ v
 }
 
 // Variants: 0 = default workgroup size and radix 16; 1 = the other workgroup size (256 <-> 512);
-// 2 = default size with radix-8 passes.
+// 2 = default size with radix-8 passes; 3 = 1024 threads (L >= 8192: one radix-8 butterfly per
+// thread, 16 waves per CU) with radix-8 passes.
 template <int L, int V>
 static int mv1d_v(const Plan& p, const double* v, double* y) {
   constexpr int NT0 = mv_threads<L>();
-  constexpr int NT = V == 1 ? (NT0 == 512 ? 256 : 512) : NT0;
-  constexpr int MAXR = V == 2 ? 8 : 16;
+  constexpr int NT = V == 1 ? (NT0 == 512 ? 256 : 512) : (V == 3 && L >= 8192 ? 1024 : NT0);
+  constexpr int MAXR = (V == 2 || V == 3) ? 8 : 16;
   k_matvec_rows<L, NT, MAXR><<<(p.Nt + 1) / 2, NT, 0, p.stream>>>(v, y, p.sym, p.twL, p.M, p.Nt,
                                                                   1, (size_t)p.M, p.live);
   RFDE_HIP(hipGetLastError());
@@ -133,6 +134,7 @@ template <int L>
 static int mv1d(const Plan& p, const double* v, double* y) {
   if (p.tv_matvec == 1) return mv1d_v<L, 1>(p, v, y);
   if (p.tv_matvec == 2) return mv1d_v<L, 2>(p, v, y);
+  if (p.tv_matvec == 3) return mv1d_v<L, 3>(p, v, y);
   return mv1d_v<L, 0>(p, v, y);
 }
 template <int L>

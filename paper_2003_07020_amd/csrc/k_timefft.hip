@@ -22,7 +22,7 @@
 
 namespace rfde {
 
-template <int N, int NB, int NT, typename C>
+template <int N, int NB, int NT, typename C, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C* __restrict__ z1,
                                                  const double* __restrict__ s,
                                                  const C* __restrict__ tw, int S,
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C
     return cmk<C>(a, b);
   };
   NoStore ns;
-  fft_io<N, +1, NT, NB, LDN, true, true, false>(buf, tw, load, ns);
+  fft_io<N, +1, NT, NB, LDN, true, true, false, MAXR>(buf, tw, load, ns);
   for (int e = threadIdx.x; e < (N / 2 + 1) * TS; e += NT) {
     const int n = e / TS, q = e - n * TS;
     const int i = i0 + q;
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C
   }
 }
 
-template <int N, int NB, int NT, typename C>
+template <int N, int NB, int NT, typename C, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_time_inv(const C* __restrict__ z2, double* __restrict__ v,
                                                  const double* __restrict__ s,
                                                  const C* __restrict__ tw, int S,
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(NT) k_time_inv(const C* __restrict__ z2, doubl
     if (i < S) row[i] = (double)c.x * sc;
     if (i + 1 < S) row[i + 1] = (double)c.y * sc;
   };
-  fft_io<N, -1, NT, NB, LDN, true, true, true>(buf, tw, load, store);
+  fft_io<N, -1, NT, NB, LDN, true, true, true, MAXR>(buf, tw, load, store);
 }
 
 // ---- Bluestein variants (Nt not a power of two, LB = Lt) ----
@@ -220,25 +220,30 @@ __global__ void __launch_bounds__(256) k_bs_kernel(int Nt, const double2* __rest
 }
 
 // Transforms per block: 128-byte row segments (NB = 8 complex128 / 16 complex64 pairs) unless
-// the ~130 KB LDS budget forces fewer; variant V halves NB V times (more, smaller workgroups).
+// the ~130 KB LDS budget forces fewer; variants 1 and 2 halve NB once and twice (more, smaller
+// workgroups); variant 3 keeps NB with 1024 threads and radix-8 passes (more waves in flight).
 template <int N, typename C, int V = 0>
 constexpr int time_nb() {
   constexpr int target = (int)sizeof(C) == 16 ? 8 : 16;
   constexpr int cap = 135168 / ((N + 1) * (int)sizeof(C));
   constexpr int nb = cap < 1 ? 1 : (cap < target ? cap : target);
-  return (nb >> V) < 1 ? 1 : (nb >> V);
+  constexpr int sh = V == 3 ? 0 : V;
+  return (nb >> sh) < 1 ? 1 : (nb >> sh);
 }
 template <int N, typename C, int V = 0>
 constexpr int time_nt() {
+  if (V == 3) return time_nb<N, C, V>() * N >= 8192 ? 1024 : 256;
   return time_nb<N, C, V>() * N >= 4096 ? 512 : 256;
 }
+template <int V> constexpr int time_maxr() { return V == 3 ? 8 : 16; }
 
 template <int N, typename C, int V>
 static int tf_fwd_v(const Plan& p, const double* v, void* z1, const C* tw) {
   constexpr int NB = time_nb<N, C, V>();
   constexpr int NT = time_nt<N, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_fwd<N, NB, NT, C><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S, p.live);
+  k_time_fwd<N, NB, NT, C, time_maxr<V>()><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S,
+                                                                         p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
@@ -247,7 +252,8 @@ static int tf_inv_v(const Plan& p, const void* z2, double* v, const C* tw) {
   constexpr int NB = time_nb<N, C, V>();
   constexpr int NT = time_nt<N, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_inv<N, NB, NT, C><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw, p.S, p.live);
+  k_time_inv<N, NB, NT, C, time_maxr<V>()><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw,
+                                                                         p.S, p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
@@ -255,12 +261,14 @@ template <int N, typename C>
 static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw) {
   if (p.tv_time == 1) return tf_fwd_v<N, C, 1>(p, v, z1, tw);
   if (p.tv_time == 2) return tf_fwd_v<N, C, 2>(p, v, z1, tw);
+  if (p.tv_time == 3) return tf_fwd_v<N, C, 3>(p, v, z1, tw);
   return tf_fwd_v<N, C, 0>(p, v, z1, tw);
 }
 template <int N, typename C>
 static int tf_inv(const Plan& p, const void* z2, double* v, const C* tw) {
   if (p.tv_time == 1) return tf_inv_v<N, C, 1>(p, z2, v, tw);
   if (p.tv_time == 2) return tf_inv_v<N, C, 2>(p, z2, v, tw);
+  if (p.tv_time == 3) return tf_inv_v<N, C, 3>(p, z2, v, tw);
   return tf_inv_v<N, C, 0>(p, z2, v, tw);
 }
 
@@ -289,6 +297,7 @@ static int tf_inv_bs_v(const Plan& p, const void* z2, double* v, const C* tw, co
 template <int LB, typename C>
 static int tf_fwd_bs(const Plan& p, const double* v, void* z1, const C* tw, const C* w,
                      const C* bh) {
+  // (variant 3 has no Bluestein instantiation: it runs the default shape)
   if (p.tv_time == 1) return tf_fwd_bs_v<LB, C, 1>(p, v, z1, tw, w, bh);
   if (p.tv_time == 2) return tf_fwd_bs_v<LB, C, 2>(p, v, z1, tw, w, bh);
   return tf_fwd_bs_v<LB, C, 0>(p, v, z1, tw, w, bh);

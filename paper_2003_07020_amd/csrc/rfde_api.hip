@@ -38,8 +38,7 @@ void free_plan(Plan* p) {
                   p->zf,     p->vbuf,    p->zbuf, p->wvec,   p->xvec,   p->Fvec,  p->red,
                   p->redout,  p->set};
   if (!p->arena)
-    for (void* b : bufs)
-      if (b) (void)hipFree(b);
+    for (void* b : bufs) dev_free(b);
   if (p->hred) (void)hipHostFree(p->hred);
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
@@ -57,8 +56,7 @@ static int palloc(Plan* p, void** ptr, size_t bytes) {
     a.used = off + bytes;
     return RFDE_OK;
   }
-  RFDE_HIP(hipMalloc(ptr, bytes));
-  return RFDE_OK;
+  return dev_alloc(ptr, bytes);
 }
 
 template <typename T>
@@ -85,7 +83,7 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
   const size_t wsz = workspace_estimate(*p);
   size_t freeb = 0, totalb = 0;
   RFDE_HIP(hipMemGetInfo(&freeb, &totalb));
-  if (!p->arena && p->factor_bytes + wsz > freeb) return RFDE_ENOMEM;
+  if (!p->arena && p->factor_bytes + wsz > freeb + dev_cached_bytes(p->device)) return RFDE_ENOMEM;
 
   size_t ws = 0;
   const int gl = p->dim == 1 ? p->M : p->Mx + p->My;

@@ -288,7 +288,7 @@ struct rfde_batch_ {
   std::vector<char> conv, failed;  // outcome per instance of the last solve
   Arena arena;                     // device memory of the waves, mapped once, reused
   ~rfde_batch_() {
-    if (arena.base) (void)hipFree(arena.base);
+    dev_free(arena.base);
   }
 };
 
@@ -307,8 +307,8 @@ struct Wave {
     for (auto e : exec)
       if (e) (void)hipGraphExecDestroy(e);
     for (Plan* p : plans) free_plan(p);
-    if (S) (void)hipFree(S);
-    if (ds) (void)hipFree(ds);
+    dev_free(S);
+    dev_free(ds);
   }
 };
 
@@ -390,8 +390,8 @@ int solve_wave(rfde_batch_& B, const std::vector<int>& idx, const double* const*
   w.exec.assign(m, nullptr);
   const auto t0 = std::chrono::steady_clock::now();
   B.arena.used = 0;  // the previous wave's plans are gone
-  RFDE_HIP(hipMalloc((void**)&w.S, sizeof(WaveState)));
-  RFDE_HIP(hipMalloc((void**)&w.ds, sizeof(BlockSet)));
+  RFDE_TRY(dev_alloc((void**)&w.S, sizeof(WaveState)));
+  RFDE_TRY(dev_alloc((void**)&w.ds, sizeof(BlockSet)));
   auto ms_since = [](std::chrono::steady_clock::time_point a) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
   };
@@ -631,7 +631,12 @@ int rfde_batch_create(rfde_batch* batch, int count, const rfde_instance* inst,
     B->bytes[i] = p.factor_bytes + workspace_estimate(p) + ((size_t)1 << 20);
   }
   size_t freeb = 0, totalb = 0;
-  if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) { delete B; return RFDE_EHIP; }
+  int dev = 0;
+  if (hipMemGetInfo(&freeb, &totalb) != hipSuccess || hipGetDevice(&dev) != hipSuccess) {
+    delete B;
+    return RFDE_EHIP;
+  }
+  freeb += dev_cached_bytes(dev);
   const size_t fixed = sizeof(WaveState) + sizeof(BlockSet) + ((size_t)64 << 20);
   const size_t cap = freeb > fixed ? (size_t)((freeb - fixed) * 0.95) : 0;
   size_t big = 0;
@@ -694,7 +699,7 @@ int rfde_batch_solve(rfde_batch batch, const double* const* u0, const double* co
     if (!u0[i] || !f[i] || !U[i]) return RFDE_EINVAL;
   RFDE_HIP(hipStreamSynchronize(batch->user));
   if (!batch->arena.base) {
-    RFDE_HIP(hipMalloc((void**)&batch->arena.base, batch->info.wave_bytes_max));
+    RFDE_TRY(dev_alloc((void**)&batch->arena.base, batch->info.wave_bytes_max));
     batch->arena.size = batch->info.wave_bytes_max;
   }
   hipStream_t st = nullptr;

@@ -141,6 +141,11 @@ inline void set_family(BlockSet& hs, int k, const Plan& p) {
   hs.live[k] = p.live;
 }
 
+// ---- device memory (rfde_mem.hip): a per-device cache of freed blocks ----
+int dev_alloc(void** ptr, size_t bytes);
+void dev_free(void* ptr);
+size_t dev_cached_bytes(int device);
+
 // ---- plan life cycle (rfde_api.hip) ----
 int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M, int Nt,
                  double T, rfde_opts o, hipStream_t stream);  // sizes only, no device work

@@ -1,8 +1,9 @@
 // Launch-shape tuner.  For a plan it times every compiled variant of the per-iteration kernels
 // on the plan's own buffers (HIP events on the plan's stream, one warm-up launch, then a few
 // timed ones) and keeps the fastest:
-//   time FFTs (steps (a) and (c)): transforms per workgroup NB, NB/2, NB/4;
-//   matvec: workgroup size 256 or 512, largest FFT radix 16 or 8;
+//   time FFTs (steps (a) and (c)): transforms per workgroup NB, NB/2, NB/4, or NB with 1024
+//   threads and radix-8 passes;
+//   matvec: workgroup size 256 or 512, largest FFT radix 16 or 8, or 1024 threads radix 8;
 //   triangular solves (exact spatial solver): one workgroup per block, or a persistent grid.
 // Results are cached per shape in the process and, when the environment variable
 // RFDE_TUNE_CACHE names a file, in that file (lines "key value"), so a shape is timed once.
@@ -102,7 +103,8 @@ int tune_plan(Plan& p, int what, rfde_tune_report* rep) {
     r.from_cache |= 1;
   } else {
     double bms = 1e300;
-    for (int v = 0; v < 3; ++v) {
+    const int nv = p.Lt == p.Nt ? 4 : 3;  // variant 3 exists for power-of-two N_t only
+    for (int v = 0; v < nv; ++v) {
       p.tv_time = v;
       double ms = 0;
       RFDE_TRY(time_ms(p, [&]() -> int {
@@ -125,7 +127,7 @@ int tune_plan(Plan& p, int what, rfde_tune_report* rep) {
       r.from_cache |= 2;
     } else {
       double bms = 1e300;
-      for (int v = 0; v < 3; ++v) {
+      for (int v = 0; v < 4; ++v) {
         p.tv_matvec = v;
         double ms = 0;
         RFDE_TRY(time_ms(p, [&]() -> int { return launch_matvec(p, p.wvec, p.xvec); }, reps, &ms));
@@ -179,7 +181,7 @@ extern "C" int rfde_plan_autotune(rfde_plan plan, rfde_tune_report* report) {
 extern "C" int rfde_plan_set_variants(rfde_plan plan, int time_variant, int matvec_variant,
                                       int trsv_grid_cap) {
   rfde::Plan* p = reinterpret_cast<rfde::Plan*>(plan);
-  if (!p || time_variant < 0 || time_variant > 2 || matvec_variant < 0 || matvec_variant > 2 ||
+  if (!p || time_variant < 0 || time_variant > 3 || matvec_variant < 0 || matvec_variant > 3 ||
       trsv_grid_cap < 0)
     return RFDE_EINVAL;
   p->tv_time = time_variant;

@@ -40,6 +40,11 @@ def opts(tol=1e-8, maxit=200, restart=30, circ_eps=0.0, precond_bits=64, spatial
     return o
 
 
+def release_cached_memory() -> int:
+    """Return the library's cached device blocks to the HIP runtime; bytes released."""
+    return int(L.lib().rfde_release_cached_memory())
+
+
 def gk(alpha: float, n: int) -> torch.Tensor:
     """g_0..g_{n-1} computed on the device."""
     g = torch.empty(n, dtype=torch.float64, device="cuda")

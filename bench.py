@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="1d_M4095_Nt1024",
                     choices=["1d_M4095_Nt1024", "1d_M63_Nt64"])
-    ap.add_argument("--forms", default="fp64,fp32,tau,learned,batched")
+    ap.add_argument("--forms", default="fp64,fp32,tau,learned,batched,2d")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--alphas", default="")
     ap.add_argument("--pinv-reps", type=int, default=10)
@@ -295,6 +295,13 @@ def measure_batched(args, dev):
     torch.cuda.synchronize()
     ms_batch = (time.perf_counter() - t0) * 1e3
     info = b.info
+    # the same with persistent grids (512 workgroups = 2 per CU, looping over the work items)
+    b.set_grid_caps(factor_cap=512, trsv_cap=512)
+    t0 = time.perf_counter()
+    _, stats_p, _ = b.solve(u0s, fs, outs)
+    torch.cuda.synchronize()
+    ms_persist = (time.perf_counter() - t0) * 1e3
+    info_p = b.info
     b.destroy()
     def factor_flops(M, Nt):
         nf, n_real = Nt // 2 + 1, (2 if Nt % 2 == 0 else 1)
@@ -335,6 +342,10 @@ def measure_batched(args, dev):
             "waves": info["waves"], "max_wave": info["max_wave"],
             "device_GB_largest_wave": round(info["device_bytes_max"] / 1e9, 2),
             "ms_total": round(ms_batch, 1), "ms_total_first_call": round(ms_first, 1),
+            "ms_total_persistent_grids": round(ms_persist, 1),
+            "ms_factor_persistent_grids": round(info_p["ms_factor"], 1),
+            "ms_solve_persistent_grids": round(info_p["ms_solve"], 1),
+            "all_converged_persistent_grids": bool(all(s.converged for s in stats_p)),
             "ms_plans_first_call": round(info_first["ms_plans"], 1),
             "ms_setup": round(info["ms_setup"], 1),
             "ms_plans": round(info["ms_plans"], 1), "ms_tune": round(info["ms_tune"], 1),
@@ -351,6 +362,74 @@ def measure_batched(args, dev):
             "iters_mean_one_by_one_fp64": round(float(np.mean(it64)), 2),
             "speedup_vs_one_by_one_fp32": round(ms32 / ms_batch, 3),
             "speedup_vs_one_by_one_fp64": round(ms64 / ms_batch, 3)}
+
+
+def measure_2d(args, dev):
+    """The 2D workload (255 x 255 grid, N_t = 256, alpha_x = 1.6, alpha_y = 1.4): time to TRR
+    1e-8 with the 2D tau preconditioner (step (b) by DST-I diagonalisation) in FP64 and in FP32
+    inside FP64 FGMRES, P^-1 applies/s, the matvec's and P^-1's HBM rates, and the FP32
+    solution's error against the oracle's FP64 march (fast diagonalisation)."""
+    import torch
+
+    from oracle import allatonce as aa
+    from oracle import twod
+    from paper_2003_07020_amd.rfde import Plan
+    from rfde_workloads import GRID_2D, gen2d
+    W = GRID_2D
+    Mx, My, Nt, gx, gy, T = W["Mx"], W["My"], W["Nt"], W["alpha_x"], W["alpha_y"], W["T"]
+    u0, f, _ = gen2d(W["seed"], Mx, My, Nt, T)
+    u0d, fd = torch.from_numpy(u0.ravel()).to(dev), torch.from_numpy(f.ravel()).to(dev)
+    N = Nt * Mx * My
+    out = {"workload": W["name"], "Mx": Mx, "My": My, "Nt": Nt, "alpha_x": gx, "alpha_y": gy,
+           "unknowns": N}
+    sols = {}
+    s = torch.cuda.current_stream()
+    for bits in (64, 32):
+        rec = []
+        U = torch.empty(N, dtype=torch.float64, device=dev)
+        for rep in range(1 + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = Plan.create_2d(gx, gy, W["kappa_x"], W["kappa_y"], 0.0, 1.0, 0.0, 1.0, Mx, My, Nt,
+                               T, tol=1e-8, precond_bits=bits)
+            _, st, _ = p.solve(u0d, fd, out=U)
+            torch.cuda.synchronize()
+            if rep > 0:
+                rec.append(((time.perf_counter() - t0) * 1e3, st.iters, st.true_rel_res))
+            if rep < args.steps:
+                p.destroy()
+        sols[bits] = U.cpu().numpy().reshape(Nt, My, Mx)
+        v = torch.randn(N, dtype=torch.float64, device=dev,
+                        generator=torch.Generator(device=dev).manual_seed(8))
+        z = torch.empty_like(v)
+        p.apply_Pinv(v, out=z)
+        ms_pinv = event_ms(lambda: p.apply_Pinv(v, out=z), 20, s)
+        p.apply_A(v, out=z)
+        ms_mv = event_ms(lambda: p.apply_A(v, out=z), 20, s)
+        p.destroy()
+        nf = Nt // 2 + 1
+        csz = 8 if bits == 32 else 16
+        # P^-1: step (a) reads v (8 B) and writes the half spectrum; step (b) reads and writes
+        # it twice (row DSTs, fused column DST-divide-DST, row DSTs); step (c) reads it, writes v
+        pinv_bytes = 16.0 * N + 6.0 * nf * Mx * My * csz
+        key = "fp64" if bits == 64 else "fp32"
+        out[key] = {"value_ms": round(float(np.mean([r[0] for r in rec])), 3),
+                    "iters": rec[0][1], "true_rel_res": rec[0][2],
+                    "precond_applies_per_s": round(1e3 / ms_pinv, 1),
+                    "ms_pinv": round(ms_pinv, 4),
+                    "pinv_GB/s": round(pinv_bytes / (ms_pinv * 1e-3) / 1e9, 1),
+                    "ms_matvec": round(ms_mv, 4),
+                    # read v, write y (16 B per unknown; two passes in practice)
+                    "matvec_GB/s": round(16.0 * N / (ms_mv * 1e-3) / 1e9, 1)}
+        progress(f"2d form {key} done")
+    hx, hy, tau = 1.0 / (Mx + 1), 1.0 / (My + 1), T / Nt
+    Tx, Ty = aa.toeplitz_T(gx, Mx), aa.toeplitz_T(gy, My)
+    cx, cy = twod.coeffs(gx, gy, W["kappa_x"], W["kappa_y"], hx, hy)
+    ref = twod.bdf2_march_2d(u0, f, Tx, Ty, cx, cy, tau)
+    for bits, key in ((64, "fp64"), (32, "fp32")):
+        out[key]["rel_err_vs_oracle"] = float(np.max(np.abs(sols[bits] - ref)) / np.max(np.abs(ref)))
+    out["speedup_fp32_vs_fp64"] = round(out["fp64"]["value_ms"] / out["fp32"]["value_ms"], 3)
+    return out
 
 
 def kernels_only(W, dev):
@@ -405,7 +484,8 @@ def main():
     batched = measure_batched(args, dev) if "batched" in forms else None
     if batched is not None:
         progress("batched form done")
-    forms = [f for f in forms if f not in ("learned", "batched")]
+    two_d = measure_2d(args, dev) if "2d" in forms else None
+    forms = [f for f in forms if f not in ("learned", "batched", "2d")]
     # fp64: the plain exact-LDL^T form; fp32: its FP32 preconditioner; tau: the paper's own step
     # (b) (DST-I diagonalisation of the tau approximation, no factors), FP64
     from paper_2003_07020_amd.rfde import release_cached_memory
@@ -473,6 +553,8 @@ def main():
         out["forms"]["learned"] = learned
     if batched is not None:
         out["forms"]["batched"] = batched
+    if two_d is not None:
+        out["forms"]["2d"] = two_d
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

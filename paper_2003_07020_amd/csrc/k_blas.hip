@@ -126,18 +126,4 @@ int launch_sub(const Plan& p, const double* a, const double* b, double* out) {
   return RFDE_OK;
 }
 
-__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    y[i] = fma(a, x[i], y[i]);
-}
-
-int launch_axpy_host(const Plan& p, double* y, const double* x, double alpha) {
-  const size_t n = p.N();
-  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
-  k_axpy<<<blocks, 256, 0, p.stream>>>(y, x, alpha, n);
-  RFDE_HIP(hipGetLastError());
-  return RFDE_OK;
-}
-
 }  // namespace rfde

@@ -160,6 +160,21 @@ __device__ __forceinline__ void acc3_init(WaveAcc3<C>& a, int i, int j,
       }
 }
 
+template <typename C>
+__device__ __forceinline__ void acc3_zero(WaveAcc3<C>& a) {
+  using R = typename mma<C>::R;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        a.p1[bi][bj][e] = (R)0;
+        a.p2[bi][bj][e] = (R)0;
+        a.p3[bi][bj][e] = (R)0;
+      }
+}
+
 template <typename C, bool D>
 __device__ __forceinline__ void acc3_finish(const WaveAcc3<C>& a, WaveAcc<C>& acc) {
 #pragma unroll
@@ -472,43 +487,31 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
   const C* Djj = fac + tile_index(j, j) * TILE_ELEMS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1, l16 = lane & 15, lq = lane >> 4;
+  // (three real MFMA products per complex product, as in the K loop; two for a dual block)
   WaveAcc<C> x;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) { x.re[bi][bj][e] = (R)0; x.im[bi][bj][e] = (R)0; }
+  {
+    WaveAcc3<C> x3;
+    acc3_zero<C>(x3);
 #pragma unroll 2
-  for (int q = 0; q < 16; ++q) {
-    const int m = 4 * q + lq;
-    R sr[2], si[2], nsi[2], br[2], bim[2];
+    for (int q = 0; q < 16; ++q) {
+      const int m = 4 * q + lq;
+      R sr[2], si[2], br[2], bim[2];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-      const C s = S[m * LDSLD + wr * 32 + bi * 16 + l16];
-      sr[bi] = s.x; si[bi] = s.y; nsi[bi] = -s.y;
-    }
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int c = wc * 32 + bj * 16 + l16;
-      C b;
-      if (c > m) b = Djj[m * TILE + c];
-      else b = cmk<C>((R)(c == m ? 1 : 0), (R)(D && c == m ? 1 : 0));
-      br[bj] = b.x; bim[bj] = b.y;
-    }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < 2; ++bi) {
+        const C s = S[m * LDSLD + wr * 32 + bi * 16 + l16];
+        sr[bi] = s.x; si[bi] = s.y;
+      }
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
-        x.re[bi][bj] = mma<C>::fma(sr[bi], br[bj], x.re[bi][bj]);
-        if constexpr (D) {
-          x.im[bi][bj] = mma<C>::fma(si[bi], bim[bj], x.im[bi][bj]);
-        } else {
-          x.re[bi][bj] = mma<C>::fma(nsi[bi], bim[bj], x.re[bi][bj]);
-          x.im[bi][bj] = mma<C>::fma(sr[bi], bim[bj], x.im[bi][bj]);
-          x.im[bi][bj] = mma<C>::fma(si[bi], br[bj], x.im[bi][bj]);
-        }
+        const int c = wc * 32 + bj * 16 + l16;
+        C b;
+        if (c > m) b = Djj[m * TILE + c];
+        else b = cmk<C>((R)(c == m ? 1 : 0), (R)(D && c == m ? 1 : 0));
+        br[bj] = b.x; bim[bj] = b.y;
       }
+      acc3_step<C, D>(x3, sr, si, br, bim);
+    }
+    acc3_finish<C, D>(x3, x);
   }
   __syncthreads();  // everyone is done reading S
   // L_ij[r][c] = X[r][c] / d_c, staged through LDS for coalesced stores
@@ -531,43 +534,30 @@ __global__ void __launch_bounds__(256) k_ldlt_panel(const BlockSet* __restrict__
   //   P_ii -= (L_ij D_j) L_ij^T,  P_ii = B_ii before column 0.
   // Only the lower triangle is used later, so the wave owning the upper-right quadrant skips.
   WaveAcc<C> dl;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) { dl.re[bi][bj][e] = (R)0; dl.im[bi][bj][e] = (R)0; }
   const bool active = !(wr == 0 && wc == 1);
-  if (active) {
+  {
+    WaveAcc3<C> d3;
+    acc3_zero<C>(d3);
+    if (active) {
 #pragma unroll 2
-    for (int q = 0; q < 16; ++q) {
-      const int m = 4 * q + lq;
-      const C d = Djj[m * (TILE + 1)];
-      R ar[2], ai[2], nai[2], br[2], bim[2];
+      for (int q = 0; q < 16; ++q) {
+        const int m = 4 * q + lq;
+        const C d = Djj[m * (TILE + 1)];
+        R ar[2], ai[2], br[2], bim[2];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi) {
-        const C a = xmul<D>(S[m * LDSLD + wr * 32 + bi * 16 + l16], d);
-        ar[bi] = a.x; ai[bi] = a.y; nai[bi] = -a.y;
-      }
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        const C b = S[m * LDSLD + wc * 32 + bj * 16 + l16];
-        br[bj] = b.x; bim[bj] = b.y;
-      }
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 2; ++bi) {
+          const C a = xmul<D>(S[m * LDSLD + wr * 32 + bi * 16 + l16], d);
+          ar[bi] = a.x; ai[bi] = a.y;
+        }
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-          dl.re[bi][bj] = mma<C>::fma(ar[bi], br[bj], dl.re[bi][bj]);
-          if constexpr (D) {
-            dl.im[bi][bj] = mma<C>::fma(ai[bi], bim[bj], dl.im[bi][bj]);
-          } else {
-            dl.re[bi][bj] = mma<C>::fma(nai[bi], bim[bj], dl.re[bi][bj]);
-            dl.im[bi][bj] = mma<C>::fma(ar[bi], bim[bj], dl.im[bi][bj]);
-            dl.im[bi][bj] = mma<C>::fma(ai[bi], br[bj], dl.im[bi][bj]);
-          }
+          const C b = S[m * LDSLD + wc * 32 + bj * 16 + l16];
+          br[bj] = b.x; bim[bj] = b.y;
         }
+        acc3_step<C, D>(d3, ar, ai, br, bim);
+      }
     }
+    acc3_finish<C, D>(d3, dl);
   }
   __syncthreads();  // S (L_ij) no longer needed
   C* Pii = fac + tile_index(i, i) * TILE_ELEMS;

@@ -193,6 +193,5 @@ int launch_multi_axpy(const Plan& p, double* w, const double* V, int nvec, const
 int launch_nrm2(const Plan& p, const double* x, double* out);
 int launch_scale_copy(const Plan& p, const double* x, double* y, const double* scal_dev, int inv);
 int launch_sub(const Plan& p, const double* a, const double* b, double* out);  // out = a - b
-int launch_axpy_host(const Plan& p, double* y, const double* x, double alpha);
 
 }  // namespace rfde

@@ -128,3 +128,17 @@ def test_one_call_solve():
     assert st.converged
     assert rel_max(to_host(U).reshape(Nt, M),
                    aa.bdf2_march(u0, f, aa.jacobian_A(alpha, kappa, h, M), tau)) < 1e-9
+
+
+def test_device_memory_cache_reuse_and_release():
+    from paper_2003_07020_amd import rfde
+    banner("memory cache")
+    rfde.release_cached_memory()
+    p = _plan(1.5, 1.0, 300, 64)
+    ptr_bytes = p.info["factor_bytes"]
+    p.destroy()
+    # the freed blocks are cached, a second plan of the same shape reuses them and is correct
+    _check_solve(1.5, 1.0, 300, 64)
+    released = rfde.release_cached_memory()
+    assert released >= ptr_bytes
+    assert rfde.release_cached_memory() == 0

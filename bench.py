@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="1d_M4095_Nt1024",
                     choices=["1d_M4095_Nt1024", "1d_M63_Nt64"])
-    ap.add_argument("--forms", default="fp64,fp32,tau,learned,batched,2d")
+    ap.add_argument("--forms", default="fp64,fp32,tau,learned,batched,2d,small")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--alphas", default="")
     ap.add_argument("--pinv-reps", type=int, default=10)
@@ -432,6 +432,46 @@ def measure_2d(args, dev):
     return out
 
 
+def measure_small(args, dev):
+    """The small configuration (M = 63, N_t = 64, alpha = 1.5, tol 1e-10): latency of one solve
+    (plan setup + solve), through rfde_solve (host-driven Arnoldi loop) and through a batch of
+    one instance (per-step HIP graphs, device-side Givens), median of 20 each."""
+    import torch
+
+    from paper_2003_07020_amd.rfde import Batch, Plan
+    from rfde_workloads import SMALL_1D, gen1d
+    W = SMALL_1D
+    M, Nt, a, kappa, T = W["M"], W["Nt"], W["alpha"], W["kappa"], W["T"]
+    u0, f, _ = gen1d(W["seed"], M, Nt, T)
+    u0d, fd = torch.from_numpy(u0).to(dev), torch.from_numpy(f.ravel()).to(dev)
+    U = torch.empty_like(fd)
+    t_plan, t_batch, it = [], [], []
+    for rep in range(21):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = Plan.create_1d(a, kappa, W["a"], W["b"], M, Nt, T, tol=W["tol"])
+        _, st, _ = p.solve(u0d, fd, out=U)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p.destroy()
+        b = Batch([dict(alpha=a, kappa=kappa, a=W["a"], b=W["b"], T=T, M=M, Nt=Nt)],
+                  tol=W["tol"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, stb, _ = b.solve([u0d], [fd], [U])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        b.destroy()
+        if rep > 0:
+            t_plan.append((t1 - t0) * 1e3)
+            t_batch.append((t3 - t2) * 1e3)
+            it.append((st.iters, stb[0].iters))
+    return {"workload": W["name"], "M": M, "Nt": Nt, "tol": W["tol"],
+            "ms_plan_solve_median": round(float(np.median(t_plan)), 3),
+            "ms_batch_of_one_median": round(float(np.median(t_batch)), 3),
+            "iters": list(it[0])}
+
+
 def kernels_only(W, dev):
     import torch
 
@@ -485,7 +525,10 @@ def main():
     if batched is not None:
         progress("batched form done")
     two_d = measure_2d(args, dev) if "2d" in forms else None
-    forms = [f for f in forms if f not in ("learned", "batched", "2d")]
+    small = measure_small(args, dev) if "small" in forms else None
+    if small is not None:
+        progress("small form done")
+    forms = [f for f in forms if f not in ("learned", "batched", "2d", "small")]
     # fp64: the plain exact-LDL^T form; fp32: its FP32 preconditioner; tau: the paper's own step
     # (b) (DST-I diagonalisation of the tau approximation, no factors), FP64
     from paper_2003_07020_amd.rfde import release_cached_memory
@@ -555,6 +598,8 @@ def main():
         out["forms"]["batched"] = batched
     if two_d is not None:
         out["forms"]["2d"] = two_d
+    if small is not None:
+        out["forms"]["small"] = small
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

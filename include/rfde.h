@@ -219,8 +219,8 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
 typedef struct {
   int time_variant;      /* time FFTs: NB >> v transforms per workgroup (v = 0..2), or 3: NB
                             with 1024 threads and radix-8 passes (power-of-two N_t only)     */
-  int matvec_variant;    /* 0 default; 1 other workgroup size; 2 largest FFT radix 8;
-                            3 1024 threads with radix 8                                        */
+  int matvec_variant;    /* 0 three-stage register FFT (L >= 256); LDS Stockham passes with
+                            1 the default workgroup size, 2 the other size, 3 radix 8         */
   int trsv_grid_cap;     /* 0 one workgroup per block; else persistent workgroups             */
   int from_cache;        /* bit 0 time, bit 1 matvec, bit 2 trsv: taken from the cache        */
   double ms_time[4];     /* timed forward + inverse time FFT per variant (0 when cached)      */

@@ -8,6 +8,7 @@
 // (Q x)_k = sqrt(2/(n+1)) (i/2) FFT_k.  P must be a power of two.
 #include <type_traits>
 
+#include "fft3.hpp"
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"
 
@@ -72,6 +73,81 @@ __global__ void __launch_bounds__(NT) k_dst_rows(C* __restrict__ z, int nrows, i
   }
 }
 
+// 1D tau solve of whole rows on the three-stage register FFT (P >= 256): row r of z (complex,
+// length n = P/2 - 1) is odd-extended, transformed, scaled and transformed back without leaving
+// registers.  X = DFT(odd(z)) is odd, so the scaled coefficients W_k = X_k d_m (m = min(k, P-k))
+// are odd too and the second DST-I, sc (i/2) DFT(W), equals -sc (i/2) times the unnormalised
+// inverse DFT of W; with the first DST's sc (i/2) the product of the constants is sc^2 / 4:
+//     d_m = (sc^2 / 4) / (lambda_r + coef sigma_m),  d_0 = d_{P/2} = 0.
+// With DUAL (N_t even) the real rows 0 and N_t/2 (real lambda, real data) share one transform
+// as its real and imaginary parts: the DFT of a real odd sequence is imaginary, so in
+// X = DFT(odd(a + i b)) the imaginary part carries a's coefficients and the real part b's, and
+// each is scaled by its own row's (real) d_m; the work list is then nrows - 1 transforms, N_t/2
+// of them for N_t even (no lone last row on the grid).
+// Rows are read and written through buffer descriptors covering exactly the row, so the odd
+// extension's zeros (indices 0 and P/2) come from the hardware range check.
+template <int P, typename C, int WAVES, bool DUAL>
+__global__ void __launch_bounds__(256, WAVES) k_dst3_scale(C* __restrict__ z, int nrows,
+                                                           const double2* __restrict__ lambda,
+                                                           const double* __restrict__ sigma,
+                                                           double coef, const C* __restrict__ tw) {
+  using E = Fft3For<P, 256>;
+  using R = typename cplx_traits<C>::real;
+  constexpr int n = P / 2 - 1;
+  __shared__ R lds[E::LDS];
+  const int nitems = DUAL ? nrows - 1 : nrows;
+  const int item0 = xcd_remap(blockIdx.x, gridDim.x) * E::NB;  // item = row, item 0 = rows 0 and nrows-1 (DUAL)
+  const double sc2 = 2.0 / (n + 1) / 4.0;
+  auto rowr = [&](int r) {
+    const bool ok = r >= 0 && r < nrows;
+    return make_rsrc(z + (ok ? (size_t)r * n : 0), ok ? n * (int)sizeof(C) : 0);
+  };
+  __amdgpu_buffer_rsrc_t rs[E::B1], rs2[E::B1];
+  bool dual[E::B1];
+#pragma unroll
+  for (int b = 0; b < E::B1; ++b) {
+    const int it = item0 + E::f_of_b1(b);
+    dual[b] = DUAL && it == 0;
+    rs[b] = rowr(it < nitems ? it : -1);
+    rs2[b] = rowr(dual[b] ? nrows - 1 : -1);
+  }
+  auto load = [&](int b, int, int idx, int n1) -> C {
+    const int j = n1 < E::N1 / 2 ? idx - 1 : P - idx - 1;
+    const R sg = n1 < E::N1 / 2 ? (R)1 : (R)-1;
+    C x;
+    if (DUAL && dual[b]) x = cmk<C>(buf_load_c<C>(rs[b], j).x, buf_load_c<C>(rs2[b], j).x);
+    else x = buf_load_c<C>(rs[b], j);
+    return cmk<C>(sg * x.x, sg * x.y);
+  };
+  auto scale = [&](int r, int m) -> double2 {  // d_m of row r as a complex number
+    const double2 lm = lambda[r];
+    const bool in = m >= 1 && m <= n;
+    const double dr = lm.x + coef * sigma[in ? m - 1 : 0], di = lm.y;
+    const double s = in ? sc2 / (dr * dr + di * di) : 0.0;
+    return make_double2(dr * s, -di * s);
+  };
+  auto pw = [&](int f, int k, C& c) {
+    const int it = min(item0 + f, nitems - 1), m = k <= P / 2 ? k : P - k;
+    if (DUAL && it == 0) {
+      const double da = scale(0, m).x, db = scale(nrows - 1, m).x;
+      c = cmk<C>((R)(c.x * db), (R)(c.y * da));
+    } else {
+      const double2 d = scale(it, m);
+      c = cmk<C>((R)(c.x * d.x - c.y * d.y), (R)(c.x * d.y + c.y * d.x));
+    }
+  };
+  auto store = [&](int b, int, int idx, int n1, C c) {
+    if (n1 >= E::N1 / 2) return;
+    if (DUAL && dual[b]) {
+      buf_store_c<C>(rs[b], idx - 1, cmk<C>(c.x, (R)0));
+      buf_store_c<C>(rs2[b], idx - 1, cmk<C>(c.y, (R)0));
+    } else {
+      buf_store_c<C>(rs[b], idx - 1, c);
+    }
+  };
+  E::run(lds, tw, load, pw, store);
+}
+
 // Columns of [nf][My][Mx] planes: one block per (frequency, tile of NB columns), columns taken
 // fastest by the threads.  DST along y, divide by lambda_n + coef_x sigma^x_ix +
 // coef_y sigma^y_iy (the x-direction DST has already been applied to the rows), DST again.
@@ -134,9 +210,30 @@ constexpr int dst_nt() {
   return dst_nb<P, C>() * P >= 4096 ? 512 : 256;
 }
 
+template <int P, typename C>
+static int dst3_scale(const Plan& p, C* z, int nrows, const double* sigma, double coef,
+                      const C* tw) {
+  using E = Fft3For<P, 256>;
+  // P = 8192 in FP64 needs more than 256 registers per lane at one wave per SIMD; two waves
+  // with a few spills run faster (71 vs 77 us at M = 4095)
+  constexpr int W = (P >= 8192 && sizeof(C) == 16) ? 2 : 1;
+  const bool dual = p.Nt % 2 == 0 && nrows == p.Nt / 2 + 1 && nrows >= 2;
+  const int items = dual ? nrows - 1 : nrows;
+  const int grid = (items + E::NB - 1) / E::NB;
+  if (dual)
+    k_dst3_scale<P, C, W, true><<<grid, 256, 0, p.stream>>>(z, nrows, p.lambda, sigma, coef, tw);
+  else
+    k_dst3_scale<P, C, W, false><<<grid, 256, 0, p.stream>>>(z, nrows, p.lambda, sigma, coef, tw);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
 template <int P, typename C, bool SCALE>
 static int dst_rows(const Plan& p, C* z, int nrows, int rows_per_freq, const double* sigma,
                     double coef, const C* tw) {
+  if constexpr (SCALE && P >= 256) {
+    if (rows_per_freq == 1) return dst3_scale<P, C>(p, z, nrows, sigma, coef, tw);
+  }
   constexpr int NB = dst_nb<P, C>();
   constexpr int NT = dst_nt<P, C>();
   k_dst_rows<P, NB, NT, C, SCALE><<<(nrows + NB - 1) / NB, NT, 0, p.stream>>>(

@@ -100,13 +100,6 @@ __device__ __forceinline__ double2 block_lambda(const BlockSet* __restrict__ set
   else return set->lambda[fm][n];
 }
 
-// Logical block index so that each XCD (blocks are dealt round-robin to 8 XCDs) walks a
-// contiguous range of logical work: neighbouring work items share operand tiles in one L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int x = b & 7, q = nb >> 3, r = nb & 7;
-  return x * q + (x < r ? x : r) + (b >> 3);
-}
-
 // Family slot k of an item map holding `item` (binary search over the start offsets).
 __device__ __forceinline__ int find_slot(const ItemMap& m, int item) {
   int lo = 0, hi = m.cnt - 1;

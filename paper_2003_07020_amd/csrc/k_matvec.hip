@@ -13,6 +13,7 @@
 //
 // Time stencil (rows of C, eq. (2.12)): level 0: v_0; level 1: 3/2 v_1 - 2 v_0;
 // level k >= 2: 3/2 v_k - 2 v_{k-1} + 1/2 v_{k-2}.
+#include "fft3.hpp"
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"
 
@@ -73,6 +74,78 @@ __global__ void __launch_bounds__(NT) k_matvec_rows(const double* __restrict__ v
   fft_io<L, +1, NT, 1, L, false, false, true, MAXR>(buf, tw, nl, store_out);
 }
 
+// Same product for L >= 256 on the three-stage register FFT: NB row pairs per workgroup, the
+// forward transform, the symbol and the inverse transform in registers with four LDS exchanges.
+// Only inputs below n (<= L/2) are non-zero and only outputs below n are kept, so the first
+// stage's upper half of inputs and the last stage's upper half of outputs are pruned at
+// compile time.  Rows are addressed through buffer descriptors whose range is the row (or
+// empty for a row past the end or a level before the first), so the hardware range check
+// replaces every bounds test: loads outside read zero and stores outside are dropped.  Row
+// pairs are dealt so that each XCD takes a contiguous range (the stencil's neighbouring levels
+// are then read from the same L2).
+template <int L, bool ONE_ROW_PER_LEVEL, int WAVES>
+__global__ void __launch_bounds__(256, WAVES)
+    k_matvec3(const double* __restrict__ v, double* __restrict__ y,
+              const double* __restrict__ sym, const double2* __restrict__ tw, int n, int rows,
+              int rows_per_level, const int* __restrict__ live) {
+  using E = Fft3For<L, 256>;
+  if (live && *live == 0) return;
+  __shared__ double lds[E::LDS];
+  const int pair0 = xcd_remap(blockIdx.x, gridDim.x) * E::NB;
+  const int nbytes = n * 8;
+  const int rpl = rows_per_level;
+  // row r of v (or y) as a buffer; empty when r is outside [0, rows)
+  auto row = [&](const double* base, int r) {
+    const bool ok = r >= 0 && r < rows;
+    return make_rsrc(base + (ok ? (size_t)r * n : 0), ok ? nbytes : 0);
+  };
+  // Per stage-1 butterfly of this thread (one row pair each): the rows it reads and writes and
+  // the BDF2 rows of C (eq. (2.12)): level 0: v_0; level k >= 1: 3/2 v_k - 2 v_{k-1} + 1/2
+  // v_{k-2} (at level 1 the v_{k-2} term reads zero through an empty descriptor).
+  struct Rows {
+    __amdgpu_buffer_rsrc_t a, b, a1, b1, a2, b2, ya, yb;
+    double ca, cb;
+  };
+  Rows rs[E::B1];
+#pragma unroll
+  for (int b = 0; b < E::B1; ++b) {
+    const int r0 = 2 * (pair0 + E::f_of_b1(b)), r1 = r0 + 1;
+    rs[b].a = row(v, r0);
+    rs[b].b = row(v, r1);
+    rs[b].a1 = row(v, r0 - rpl);
+    rs[b].b1 = rpl == 1 ? rs[b].a : row(v, r1 - rpl);
+    rs[b].a2 = row(v, r0 - 2 * rpl);
+    rs[b].b2 = rpl == 1 ? rs[b].a1 : row(v, r1 - 2 * rpl);
+    rs[b].ya = row(y, r0);
+    rs[b].yb = row(y, r1);
+    rs[b].ca = r0 < rpl ? 1.0 : 1.5;
+    rs[b].cb = r1 < rpl ? 1.0 : 1.5;
+  }
+  auto load = [&](int b, int, int idx, int n1) -> double2 {
+    if (n1 >= E::N1 / 2) return make_double2(0.0, 0.0);
+    return make_double2(buf_load(rs[b].a, idx), buf_load(rs[b].b, idx));
+  };
+  auto pw = [&](int, int k, double2& c) {
+    const double s = sym[k <= L / 2 ? k : L - k];
+    c.x *= s;
+    c.y *= s;
+  };
+  auto store = [&](int b, int, int idx, int n1, double2 c) {
+    if (n1 >= E::N1 / 2) return;
+    const Rows& r = rs[b];
+    const double va = buf_load(r.a, idx), va1 = buf_load(r.a1, idx);
+    const double s0 = r.ca * va - 2.0 * va1 + 0.5 * buf_load(r.a2, idx);
+    // one time level per row: the pair's rows are levels k, k+1 and share v_k, v_{k-1}
+    const double s1 = ONE_ROW_PER_LEVEL
+                          ? r.cb * buf_load(r.b, idx) - 2.0 * va + 0.5 * va1
+                          : r.cb * buf_load(r.b, idx) - 2.0 * buf_load(r.b1, idx) +
+                                0.5 * buf_load(r.b2, idx);
+    buf_store(r.ya, idx, s0 + c.x);
+    buf_store(r.yb, idx, s1 + c.y);
+  };
+  E::run(lds, tw, load, pw, store);
+}
+
 // 2D, y direction: for one time level and a tile of 2*NB adjacent columns, NB complex transforms
 // of length L along y (column pairs packed as real/imaginary parts, batch index fastest so the
 // row segments are read and written contiguously).  Adds (tau c_y T_y along y) v into y.
@@ -117,18 +190,37 @@ __global__ void __launch_bounds__(NT) k_matvec_2d_y(const double* __restrict__ v
   fft_io<L, +1, NT, NB, LDN, true, false, true>(buf, tw, nl, store_out);
 }
 
-// Variants: 0 = default workgroup size and radix 16; 1 = the other workgroup size (256 <-> 512);
-// 2 = default size with radix-8 passes; 3 = 1024 threads (L >= 8192: one radix-8 butterfly per
-// thread, 16 waves per CU) with radix-8 passes.
-template <int L, int V>
-static int mv1d_v(const Plan& p, const double* v, double* y) {
-  constexpr int NT0 = mv_threads<L>();
-  constexpr int NT = V == 1 ? (NT0 == 512 ? 256 : 512) : (V == 3 && L >= 8192 ? 1024 : NT0);
-  constexpr int MAXR = (V == 2 || V == 3) ? 8 : 16;
-  k_matvec_rows<L, NT, MAXR><<<(p.Nt + 1) / 2, NT, 0, p.stream>>>(v, y, p.sym, p.twL, p.M, p.Nt,
-                                                                  1, (size_t)p.M, p.live);
+// Variants: 0 = three-stage register FFT (L >= 256; smaller L: the Stockham kernel);
+// 1 = Stockham passes with the default workgroup size and radix 16; 2 = the other workgroup size
+// (256 <-> 512); 3 = radix-8 passes (1024 threads for L >= 8192).
+template <int L>
+static int mv_rows(const Plan& p, const double* v, double* y, int n, int rows, int rpl,
+                   const int* live) {
+  using E = Fft3For<L, 256>;
+  // L = 8192 needs more than 256 registers per lane at one wave per SIMD; bounding it to two
+  // waves costs a few spills but hides latency better (measured 35 vs 44 us at M = 4095).
+  constexpr int WAVES = L >= 8192 ? 2 : 1;
+  const int groups = ((rows + 1) / 2 + E::NB - 1) / E::NB;
+  if (rpl == 1)
+    k_matvec3<L, true, WAVES><<<groups, 256, 0, p.stream>>>(v, y, p.sym, p.twL, n, rows, 1, live);
+  else
+    k_matvec3<L, false, 1><<<groups, 256, 0, p.stream>>>(v, y, p.sym, p.twL, n, rows, rpl, live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
+}
+template <int L, int V>
+static int mv1d_v(const Plan& p, const double* v, double* y) {
+  if constexpr (V == 0 && L >= 256) {
+    return mv_rows<L>(p, v, y, p.M, p.Nt, 1, p.live);
+  } else {
+    constexpr int NT0 = mv_threads<L>();
+    constexpr int NT = V == 2 ? (NT0 == 512 ? 256 : 512) : (V == 3 && L >= 8192 ? 1024 : NT0);
+    constexpr int MAXR = V == 3 ? 8 : 16;
+    k_matvec_rows<L, NT, MAXR><<<(p.Nt + 1) / 2, NT, 0, p.stream>>>(v, y, p.sym, p.twL, p.M, p.Nt,
+                                                                    1, (size_t)p.M, p.live);
+    RFDE_HIP(hipGetLastError());
+    return RFDE_OK;
+  }
 }
 template <int L>
 static int mv1d(const Plan& p, const double* v, double* y) {
@@ -139,12 +231,16 @@ static int mv1d(const Plan& p, const double* v, double* y) {
 }
 template <int L>
 static int mv2dx(const Plan& p, const double* v, double* y) {
-  constexpr int NT = mv_threads<L>();
   const int rows = p.Nt * p.My;
-  k_matvec_rows<L, NT><<<(rows + 1) / 2, NT, 0, p.stream>>>(v, y, p.sym, p.twL, p.Mx, rows, p.My,
-                                                            (size_t)p.Mx * p.My, nullptr);
-  RFDE_HIP(hipGetLastError());
-  return RFDE_OK;
+  if constexpr (L >= 256) {
+    return mv_rows<L>(p, v, y, p.Mx, rows, p.My, nullptr);
+  } else {
+    constexpr int NT = mv_threads<L>();
+    k_matvec_rows<L, NT><<<(rows + 1) / 2, NT, 0, p.stream>>>(v, y, p.sym, p.twL, p.Mx, rows,
+                                                              p.My, (size_t)p.Mx * p.My, nullptr);
+    RFDE_HIP(hipGetLastError());
+    return RFDE_OK;
+  }
 }
 template <int L>
 static int mv2dy(const Plan& p, const double* v, double* y) {

@@ -3,7 +3,8 @@
 // timed ones) and keeps the fastest:
 //   time FFTs (steps (a) and (c)): transforms per workgroup NB, NB/2, NB/4, or NB with 1024
 //   threads and radix-8 passes;
-//   matvec: workgroup size 256 or 512, largest FFT radix 16 or 8, or 1024 threads radix 8;
+//   matvec: the three-stage register FFT (L >= 256), or LDS Stockham passes with the default
+//   workgroup size, the other size (256 <-> 512), or radix 8 (1024 threads for L = 8192);
 //   triangular solves (exact spatial solver): one workgroup per block, or a persistent grid.
 // Results are cached per shape in the process and, when the environment variable
 // RFDE_TUNE_CACHE names a file, in that file (lines "key value"), so a shape is timed once.

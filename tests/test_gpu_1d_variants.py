@@ -7,6 +7,8 @@ import os
 import numpy as np
 import pytest
 
+import paper_2003_07020_amd._lib as capi
+
 from gpu_util import banner, rel_max, to_dev, to_host
 from oracle import allatonce as aa
 from oracle import precond as pc
@@ -53,14 +55,29 @@ def test_fp32_factor_and_solve(alpha, M, Nt):
     assert rel_max(U, aa.bdf2_march(u0, f, A, tau)) < 1e-9
 
 
-@pytest.mark.parametrize("alpha,M,Nt", [(1.5, 63, 64), (1.2, 127, 8), (1.9, 255, 32)])
+@pytest.mark.parametrize("alpha,M,Nt", [(1.5, 63, 64), (1.2, 127, 8), (1.9, 255, 32),
+                                         (1.6, 1023, 8), (1.4, 2047, 4), (1.8, 4095, 8),
+                                         (1.7, 511, 7), (1.3, 1023, 5)])
 @pytest.mark.parametrize("bits", [64, 32])
 def test_tau_step_b_1d(alpha, M, Nt, bits):
     banner(f"tau1d bits={bits} alpha={alpha} M={M} Nt={Nt}")
     p = _plan(alpha, 1.0, M, Nt, spatial="tau", precond_bits=bits)
     h, tau = aa.mesh(0.0, 1.0, M, 1.0, Nt)
     eps = pc.default_eps(tau)
-    sig_A = -(1.0 / h**alpha) * pc.tau_eigenvalues(gk_recurrence(alpha, M))
+    g = gk_recurrence(alpha, M)
+    # sigma_i = (Q chat)_i / Q_{i1} (eq. (3.10)) cancels heavily for the smallest eigenvalues at
+    # large M (sigma_1 = 2.5e-6 from terms of size ~1e-2 at alpha = 1.8, M = 4095), so two FP64
+    # evaluations in different summation orders agree only to the rounding bound of that sum:
+    # |d sigma_i| <= (M + 4 log2 P) u sum_k |Q_ik chat_k| / |Q_i1| (dense sum in the oracle,
+    # FFT of length P = 2(M+1) on the GPU).
+    sig_gpu = to_host(p.export(capi.EXPORT_TAU_SIGMA))
+    sig_or = pc.tau_eigenvalues(g)
+    Q = pc.dst_matrix(M)
+    bound = (np.abs(Q) @ np.abs(pc.tau_first_column(g))) / np.abs(Q[:, 0])
+    u = np.finfo(np.float64).eps / 2
+    assert np.all(np.abs(sig_gpu - sig_or) <= (M + 4 * np.log2(2 * (M + 1))) * u * bound)
+    # step (b) itself, given the plan's sigma
+    sig_A = -(1.0 / h**alpha) * sig_gpu
     v = wl.random_vector(43, Nt * M).reshape(Nt, M)
     z1 = pc.step_a(v, eps)
     z2 = to_host(p.step_b(to_dev(z1.ravel()))).reshape(-1, M)

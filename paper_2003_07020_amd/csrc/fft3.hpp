@@ -18,6 +18,8 @@
 // (reads of B, odd stride N3 + 1); the paddings keep the 16 and 32 consecutive lanes of one
 // 8-byte access in distinct banks for the radix splits instantiated here.
 #pragma once
+#include <type_traits>
+
 #include "fft_lds.hpp"
 
 namespace rfde {
@@ -168,11 +170,11 @@ struct Fft3 {
     return addrB(f, k1, k2, i % N3);
   }
 
-  // Transform of stage-1 butterfly b of this thread, as a wave-uniform (scalar) value: T1 >= 64
-  // and NT a multiple of T1, so every lane of a wave works on the same transform.
+  // Transform of stage-1 butterfly b of this thread, as a wave-uniform (scalar) value: T1 is a
+  // multiple of 64, so every lane of a wave works on the same transform.
   __device__ static __forceinline__ int f_of_b1(int b) {
-    static_assert(T1 % 64 == 0 && NT % T1 == 0, "stage-1 transforms must be wave-uniform");
-    return b * (NT / T1) + __builtin_amdgcn_readfirstlane((int)threadIdx.x / T1);
+    static_assert(T1 % 64 == 0 && NT % 64 == 0, "stage-1 transforms must be wave-uniform");
+    return __builtin_amdgcn_readfirstlane(((int)threadIdx.x + b * NT) / T1);
   }
 
   // Forward stage 1: inputs from load(b, f, idx, n1), idx = n1 T1 + t the natural index of
@@ -270,9 +272,15 @@ template <> struct Split3<512> { static constexpr int N1 = 8, N2 = 8, N3 = 8, NB
 template <> struct Split3<1024> { static constexpr int N1 = 16, N2 = 8, N3 = 8, NB = 4; };
 template <> struct Split3<2048> { static constexpr int N1 = 8, N2 = 16, N3 = 16, NB = 2; };
 template <> struct Split3<4096> { static constexpr int N1 = 16, N2 = 16, N3 = 16, NB = 1; };
-template <> struct Split3<8192> { static constexpr int N1 = 32, N2 = 16, N3 = 16, NB = 1; };
+template <> struct Split3<8192> { static constexpr int N1 = 16, N2 = 16, N3 = 32, NB = 1; };
 
 template <int N, int NT = 256>
 using Fft3For = Fft3<Split3<N>::N1, Split3<N>::N2, Split3<N>::N3, Split3<N>::NB, NT>;
+
+// Split with the radix-32 stage first for N = 8192: a pointwise step that needs many registers
+// of its own then runs on two 16-point butterflies instead of one 32-point one.
+template <int N, int NT = 256>
+using Fft3WideMid = typename std::conditional<N == 8192, Fft3<32, 16, 16, 1, NT>,
+                                              Fft3For<N, NT>>::type;
 
 }  // namespace rfde

@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(NT) k_dst_rows(C* __restrict__ z, int nrows, i
   using R = typename cplx_traits<C>::real;
   constexpr int n = P / 2 - 1;
   __shared__ C buf[NB * P];
-  const int row0 = blockIdx.x * NB;
+  const int row0 = xcd_remap(blockIdx.x, gridDim.x) * NB;
   const R sc = (R)sqrt(2.0 / (n + 1));
   auto load = [&](int f, int idx) -> C {
     const int row = row0 + f;
@@ -87,29 +87,34 @@ __global__ void __launch_bounds__(NT) k_dst_rows(C* __restrict__ z, int nrows, i
 // Rows are read and written through buffer descriptors covering exactly the row, so the odd
 // extension's zeros (indices 0 and P/2) come from the hardware range check.
 template <int P, typename C, int WAVES, bool DUAL>
-__global__ void __launch_bounds__(256, WAVES) k_dst3_scale(C* __restrict__ z, int nrows,
+__global__ void __launch_bounds__(256, WAVES) k_dst3_scale(const C* zin, C* zout, int nrows,
                                                            const double2* __restrict__ lambda,
                                                            const double* __restrict__ sigma,
                                                            double coef, const C* __restrict__ tw) {
-  using E = Fft3For<P, 256>;
+  using E = Fft3WideMid<P, 256>;
   using R = typename cplx_traits<C>::real;
   constexpr int n = P / 2 - 1;
   __shared__ R lds[E::LDS];
   const int nitems = DUAL ? nrows - 1 : nrows;
-  const int item0 = xcd_remap(blockIdx.x, gridDim.x) * E::NB;  // item = row, item 0 = rows 0 and nrows-1 (DUAL)
+  // item = row; with DUAL item 0 is the pair of rows 0 and nrows - 1
+  const int item0 = xcd_remap(blockIdx.x, gridDim.x) * E::NB;
   const double sc2 = 2.0 / (n + 1) / 4.0;
-  auto rowr = [&](int r) {
+  auto rowr = [&](const C* z, int r) {
     const bool ok = r >= 0 && r < nrows;
     return make_rsrc(z + (ok ? (size_t)r * n : 0), ok ? n * (int)sizeof(C) : 0);
   };
-  __amdgpu_buffer_rsrc_t rs[E::B1], rs2[E::B1];
+  // rows read (rs, rs2) and written (ws, ws2); zin == zout is allowed (each workgroup reads all
+  // of its rows before it writes any)
+  __amdgpu_buffer_rsrc_t rs[E::B1], rs2[E::B1], ws[E::B1], ws2[E::B1];
   bool dual[E::B1];
 #pragma unroll
   for (int b = 0; b < E::B1; ++b) {
     const int it = item0 + E::f_of_b1(b);
     dual[b] = DUAL && it == 0;
-    rs[b] = rowr(it < nitems ? it : -1);
-    rs2[b] = rowr(dual[b] ? nrows - 1 : -1);
+    rs[b] = rowr(zin, it < nitems ? it : -1);
+    rs2[b] = rowr(zin, dual[b] ? nrows - 1 : -1);
+    ws[b] = rowr(zout, it < nitems ? it : -1);
+    ws2[b] = rowr(zout, dual[b] ? nrows - 1 : -1);
   }
   auto load = [&](int b, int, int idx, int n1) -> C {
     const int j = n1 < E::N1 / 2 ? idx - 1 : P - idx - 1;
@@ -119,11 +124,17 @@ __global__ void __launch_bounds__(256, WAVES) k_dst3_scale(C* __restrict__ z, in
     else x = buf_load_c<C>(rs[b], j);
     return cmk<C>(sg * x.x, sg * x.y);
   };
-  auto scale = [&](int r, int m) -> double2 {  // d_m of row r as a complex number
+  // d_m of row r as a complex number; 1 / |den|^2 by the hardware reciprocal refined with two
+  // Newton steps r <- r + r (1 - q r) (each at least doubles the correct bits)
+  auto scale = [&](int r, int m) -> double2 {
     const double2 lm = lambda[r];
     const bool in = m >= 1 && m <= n;
     const double dr = lm.x + coef * sigma[in ? m - 1 : 0], di = lm.y;
-    const double s = in ? sc2 / (dr * dr + di * di) : 0.0;
+    const double q = dr * dr + di * di;
+    double rq = __builtin_amdgcn_rcp(q);
+    rq = fma(rq, fma(-q, rq, 1.0), rq);
+    rq = fma(rq, fma(-q, rq, 1.0), rq);
+    const double s = in ? sc2 * rq : 0.0;
     return make_double2(dr * s, -di * s);
   };
   auto pw = [&](int f, int k, C& c) {
@@ -139,10 +150,10 @@ __global__ void __launch_bounds__(256, WAVES) k_dst3_scale(C* __restrict__ z, in
   auto store = [&](int b, int, int idx, int n1, C c) {
     if (n1 >= E::N1 / 2) return;
     if (DUAL && dual[b]) {
-      buf_store_c<C>(rs[b], idx - 1, cmk<C>(c.x, (R)0));
-      buf_store_c<C>(rs2[b], idx - 1, cmk<C>(c.y, (R)0));
+      buf_store_c<C>(ws[b], idx - 1, cmk<C>(c.x, (R)0));
+      buf_store_c<C>(ws2[b], idx - 1, cmk<C>(c.y, (R)0));
     } else {
-      buf_store_c<C>(rs[b], idx - 1, c);
+      buf_store_c<C>(ws[b], idx - 1, c);
     }
   };
   E::run(lds, tw, load, pw, store);
@@ -162,7 +173,8 @@ __global__ void __launch_bounds__(NT) k_dst_cols(C* __restrict__ z, int Mx,
   constexpr int LDN = P + 1;
   __shared__ C buf[NB * LDN];
   const int ntile = (Mx + NB - 1) / NB;
-  const int fq = blockIdx.x / ntile, x0 = (blockIdx.x % ntile) * NB;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring tiles share cache lines
+  const int fq = bid / ntile, x0 = (bid % ntile) * NB;
   C* plane = z + (size_t)fq * n * Mx;
   const R sc = (R)sqrt(2.0 / (n + 1));
   const double2 lam = lambda[fq];
@@ -211,9 +223,9 @@ constexpr int dst_nt() {
 }
 
 template <int P, typename C>
-static int dst3_scale(const Plan& p, C* z, int nrows, const double* sigma, double coef,
-                      const C* tw) {
-  using E = Fft3For<P, 256>;
+static int dst3_scale(const Plan& p, const C* zin, C* z, int nrows, const double* sigma,
+                      double coef, const C* tw) {
+  using E = Fft3WideMid<P, 256>;
   // P = 8192 in FP64 needs more than 256 registers per lane at one wave per SIMD; two waves
   // with a few spills run faster (71 vs 77 us at M = 4095)
   constexpr int W = (P >= 8192 && sizeof(C) == 16) ? 2 : 1;
@@ -221,9 +233,11 @@ static int dst3_scale(const Plan& p, C* z, int nrows, const double* sigma, doubl
   const int items = dual ? nrows - 1 : nrows;
   const int grid = (items + E::NB - 1) / E::NB;
   if (dual)
-    k_dst3_scale<P, C, W, true><<<grid, 256, 0, p.stream>>>(z, nrows, p.lambda, sigma, coef, tw);
+    k_dst3_scale<P, C, W, true><<<grid, 256, 0, p.stream>>>(zin, z, nrows, p.lambda, sigma, coef,
+                                                            tw);
   else
-    k_dst3_scale<P, C, W, false><<<grid, 256, 0, p.stream>>>(z, nrows, p.lambda, sigma, coef, tw);
+    k_dst3_scale<P, C, W, false><<<grid, 256, 0, p.stream>>>(zin, z, nrows, p.lambda, sigma, coef,
+                                                             tw);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
@@ -231,9 +245,6 @@ static int dst3_scale(const Plan& p, C* z, int nrows, const double* sigma, doubl
 template <int P, typename C, bool SCALE>
 static int dst_rows(const Plan& p, C* z, int nrows, int rows_per_freq, const double* sigma,
                     double coef, const C* tw) {
-  if constexpr (SCALE && P >= 256) {
-    if (rows_per_freq == 1) return dst3_scale<P, C>(p, z, nrows, sigma, coef, tw);
-  }
   constexpr int NB = dst_nb<P, C>();
   constexpr int NT = dst_nt<P, C>();
   k_dst_rows<P, NB, NT, C, SCALE><<<(nrows + NB - 1) / NB, NT, 0, p.stream>>>(
@@ -271,15 +282,31 @@ static int dst_cols(const Plan& p, C* z, const C* tw) {
 
 // Twiddle tables for the DST lengths live after the L tables: they are built on demand by the
 // plan (p.twD holds 2 (Mx+1) entries then 2 (My+1) in 2D; 2 (M+1) in 1D), double and float.
+template <int P, typename C>
+static int dst_1d(const Plan& p, const C* zin, C* z, const C* tw) {
+  if constexpr (P >= 256) {
+    return dst3_scale<P, C>(p, zin, z, p.nf, p.sigma, p.coef, tw);
+  } else {
+    if (zin != z)
+      RFDE_HIP(hipMemcpyAsync(z, zin, (size_t)p.nf * p.S * sizeof(C), hipMemcpyDeviceToDevice,
+                              p.stream));
+    return dst_rows<P, C, true>(p, z, p.nf, 1, p.sigma, p.coef, tw);
+  }
+}
+
 template <typename C>
-static int tau_solve_t(const Plan& p, void* zio) {
+static int tau_solve_t(const Plan& p, const void* zinv, void* zio) {
   C* z = (C*)zio;
+  const C* zin = (const C*)zinv;
   const bool f32 = std::is_same<C, float2>::value;
   if (p.dim == 1) {
     const int P = 2 * (p.M + 1);
     const C* tw = f32 ? (const C*)((double2*)p.twD + P) : (const C*)p.twD;
-    RFDE_P_SWITCH(P, dst_rows, C, true>(p, z, p.nf, 1, p.sigma, p.coef, tw));
+    RFDE_P_SWITCH(P, dst_1d, C>(p, zin, z, tw));
   }
+  if (zin != z)
+    RFDE_HIP(hipMemcpyAsync(z, zin, (size_t)p.nf * p.S * sizeof(C), hipMemcpyDeviceToDevice,
+                            p.stream));
   const int Px = 2 * (p.Mx + 1), Py = 2 * (p.My + 1);
   const double2* twd = p.twD;
   const C* twx = f32 ? (const C*)(twd + Px + Py) : (const C*)twd;
@@ -296,12 +323,8 @@ static int tau_solve_t(const Plan& p, void* zio) {
 }
 
 int launch_tau_solve(const Plan& p, const void* zin, void* zout) {
-  const size_t csz = p.opts.precond_bits == 32 ? 8 : 16;
-  if (zin != zout)
-    RFDE_HIP(hipMemcpyAsync(zout, zin, (size_t)p.nf * p.S * csz, hipMemcpyDeviceToDevice,
-                            p.stream));
-  if (p.opts.precond_bits == 32) return tau_solve_t<float2>(p, zout);
-  return tau_solve_t<double2>(p, zout);
+  if (p.opts.precond_bits == 32) return tau_solve_t<float2>(p, zin, zout);
+  return tau_solve_t<double2>(p, zin, zout);
 }
 
 }  // namespace rfde

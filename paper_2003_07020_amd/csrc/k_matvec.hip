@@ -159,7 +159,8 @@ __global__ void __launch_bounds__(NT) k_matvec_2d_y(const double* __restrict__ v
   __shared__ double2 buf[NB * LDN];
   constexpr int TS = 2 * NB;
   const int ntile = (Mx + TS - 1) / TS;
-  const int k = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring tiles share cache lines
+  const int k = bid / ntile, tile = bid % ntile;
   const int x0 = tile * TS;
   const size_t base = (size_t)k * Mx * My;
   auto load = [&](int f, int iy) -> double2 {

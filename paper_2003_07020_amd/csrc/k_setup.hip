@@ -132,21 +132,36 @@ int launch_time_data(int Nt, double eps, double* s, double2* lambda, hipStream_t
 // Eigenvalues of the natural tau approximation of the symmetric Toeplitz matrix with first
 // column g_0..g_{n-1}: chat_k = g_k - g_{k+2} (k <= n-3), chat_{n-2} = g_{n-2}, chat_{n-1} = g_{n-1};
 // sigma_i = sum_{j=1}^{n} chat_{j-1} sin(pi i j/(n+1)) / sin(pi i/(n+1)), i = 1..n (eq. (3.10)).
-__global__ void k_tau_sigma(const double* __restrict__ g, int n, double* __restrict__ sigma) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
-  if (i > n) return;
+// One workgroup per i; the sines come from the twiddle table of length P = 2(n+1)
+// (tw[m] = exp(-2 pi i m / P), so sin(pi i j / (n+1)) = -Im tw[(i j) mod P]) and the partial
+// sums are combined in a fixed order (the result does not depend on scheduling).
+__global__ void __launch_bounds__(256) k_tau_sigma(const double* __restrict__ g, int n,
+                                                   const double2* __restrict__ tw,
+                                                   double* __restrict__ sigma) {
+  __shared__ double part[256];
+  const int i = blockIdx.x + 1;
   const int P = 2 * (n + 1);
+  const int step = (int)((256LL * i) % P);
+  int m = (int)((long long)i * (threadIdx.x + 1) % P);
   double acc = 0.0;
-  for (int j = 1; j <= n; ++j) {
+  for (int j = threadIdx.x + 1; j <= n; j += 256) {
     const int k = j - 1;
     const double c = (k <= n - 3) ? g[k] - g[k + 2] : g[k];
-    acc += c * sinpi((double)((long long)i * j % P) / (n + 1));
+    acc += c * -tw[m].y;
+    m += step;
+    if (m >= P) m -= P;
   }
-  sigma[i - 1] = acc / sinpi((double)i / (n + 1));
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sigma[i - 1] = part[0] / -tw[i].y;
 }
 
-int launch_tau_sigma(const double* g, int n, const double2*, double* sigma, hipStream_t st) {
-  k_tau_sigma<<<(n + 255) / 256, 256, 0, st>>>(g, n, sigma);
+int launch_tau_sigma(const double* g, int n, const double2* tw, double* sigma, hipStream_t st) {
+  k_tau_sigma<<<n, 256, 0, st>>>(g, n, tw, sigma);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

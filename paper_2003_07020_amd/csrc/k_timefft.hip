@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C
   constexpr int LDN = N + 1;
   __shared__ C buf[NB * LDN];
   constexpr int TS = 2 * NB;
-  const int i0 = blockIdx.x * TS;
+  const int i0 = xcd_remap(blockIdx.x, gridDim.x) * TS;  // neighbours share lines: one XCD
   auto load = [&](int f, int j) -> C {
     const int i = i0 + 2 * f;
     const double* row = v + (size_t)j * S;
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(NT) k_time_inv(const C* __restrict__ z2, doubl
   constexpr int LDN = N + 1;
   __shared__ C buf[NB * LDN];
   constexpr int TS = 2 * NB;
-  const int i0 = blockIdx.x * TS;
+  const int i0 = xcd_remap(blockIdx.x, gridDim.x) * TS;  // neighbours share lines: one XCD
   // Z_n = P_n + i Q_n with P, Q the half spectra of points 2p, 2p+1, extended by
   // P_{N-n} = conj(P_n); imaginary parts at n = 0 and n = N/2 are dropped.
   auto load = [&](int f, int n) -> C {
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(NT) k_time_fwd_bs(const double* __restrict__ v
   constexpr int LDN = LB + 1;
   __shared__ C buf[NB * LDN];
   constexpr int TS = 2 * NB;
-  const int i0 = blockIdx.x * TS;
+  const int i0 = xcd_remap(blockIdx.x, gridDim.x) * TS;  // neighbours share lines: one XCD
   auto load = [&](int f, int j) -> C {
     if (j >= Nt) return cmk<C>((R)0, (R)0);
     const int i = i0 + 2 * f;
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(NT) k_time_inv_bs(const C* __restrict__ z2, do
   constexpr int LDN = LB + 1;
   __shared__ C buf[NB * LDN];
   constexpr int TS = 2 * NB;
-  const int i0 = blockIdx.x * TS;
+  const int i0 = xcd_remap(blockIdx.x, gridDim.x) * TS;  // neighbours share lines: one XCD
   const int half = Nt / 2;
   // y_n = conj(Z_n) w_n with Z_n = P_n + i Q_n rebuilt from the half spectra as in k_time_inv
   // (only an even Nt has a self-conjugate n = Nt/2).

@@ -132,8 +132,6 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
     RFDE_TRY(launch_gk(p->alpha, p->M, p->g, st));
     RFDE_TRY(launch_twiddles(p->twL, p->L, st));
     RFDE_TRY(launch_symbol(p->g, p->M, p->L, p->coef / p->L, p->twL, p->sym, st));
-    if (p->opts.spatial == RFDE_SPATIAL_TAU)
-      RFDE_TRY(launch_tau_sigma(p->g, p->M, nullptr, p->sigma, st));
   } else {
     RFDE_TRY(launch_gk(p->alpha_x, p->Mx, p->g, st));
     RFDE_TRY(launch_gk(p->alpha_y, p->My, p->g + p->Mx, st));
@@ -142,8 +140,6 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
     RFDE_TRY(launch_symbol(p->g, p->Mx, p->Lx, p->coef_x / p->Lx, p->twL, p->sym, st));
     RFDE_TRY(launch_symbol(p->g + p->Mx, p->My, p->Ly, p->coef_y / p->Ly, p->twL + p->Lx,
                            p->sym + (p->Lx / 2 + 1), st));
-    RFDE_TRY(launch_tau_sigma(p->g, p->Mx, nullptr, p->sigma, st));
-    RFDE_TRY(launch_tau_sigma(p->g + p->Mx, p->My, nullptr, p->sigma + p->Mx, st));
   }
   if (p->opts.spatial == RFDE_SPATIAL_TAU) {
     // DST twiddles: double tables (length 2(n+1) per axis), then the same in float
@@ -158,6 +154,13 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
     if (P1) {
       RFDE_TRY(launch_twiddles(p->twD + P0, P1, st));
       RFDE_TRY(launch_twiddles32(tf + P0, P1, st));
+    }
+    // tau eigenvalues (eq. (3.10)), sines taken from the DST tables
+    if (p->dim == 1) {
+      RFDE_TRY(launch_tau_sigma(p->g, p->M, p->twD, p->sigma, st));
+    } else {
+      RFDE_TRY(launch_tau_sigma(p->g, p->Mx, p->twD, p->sigma, st));
+      RFDE_TRY(launch_tau_sigma(p->g + p->Mx, p->My, p->twD + P0, p->sigma + p->Mx, st));
     }
   }
   RFDE_TRY(launch_twiddles(p->twNt, p->Lt, st));

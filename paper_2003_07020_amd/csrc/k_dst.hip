@@ -217,9 +217,11 @@ constexpr int dst_nb() {
   constexpr int cap = 135168 / ((P + 1) * (int)sizeof(C));
   return cap < 1 ? 1 : (cap < target ? cap : target);
 }
+// one radix-16 butterfly per thread (NB P / 16, between 64 and 512)
 template <int P, typename C>
 constexpr int dst_nt() {
-  return dst_nb<P, C>() * P >= 4096 ? 512 : 256;
+  constexpr int t = dst_nb<P, C>() * P / 16;
+  return t < 64 ? 64 : (t > 512 ? 512 : t);
 }
 
 template <int P, typename C>

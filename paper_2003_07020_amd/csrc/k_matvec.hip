@@ -247,7 +247,7 @@ template <int L>
 static int mv2dy(const Plan& p, const double* v, double* y) {
   // tile of 2*NB columns: 128-byte row segments where the LDS budget (~130 KB) allows
   constexpr int NB = (8 * (L + 1) * 16 <= 135168) ? 8 : ((4 * (L + 1) * 16 <= 135168) ? 4 : ((2 * (L + 1) * 16 <= 135168) ? 2 : 1));
-  constexpr int NT = (NB * L >= 2048) ? 512 : 256;
+  constexpr int NT = (NB * L / 16 < 64) ? 64 : (NB * L / 16 > 512 ? 512 : NB * L / 16);
   const int ntile = (p.Mx + 2 * NB - 1) / (2 * NB);
   const double* symy = p.sym + (p.Lx / 2 + 1);
   const double2* twy = p.twL + p.Lx;

@@ -230,10 +230,13 @@ constexpr int time_nb() {
   constexpr int sh = V == 3 ? 0 : V;
   return (nb >> sh) < 1 ? 1 : (nb >> sh);
 }
+// Threads: one radix-16 butterfly each (NB N / 16, between 64 and 512); variant 3: 1024 threads
+// for NB N >= 8192.
 template <int N, typename C, int V = 0>
 constexpr int time_nt() {
   if (V == 3) return time_nb<N, C, V>() * N >= 8192 ? 1024 : 256;
-  return time_nb<N, C, V>() * N >= 4096 ? 512 : 256;
+  constexpr int t = time_nb<N, C, V>() * N / 16;
+  return t < 64 ? 64 : (t > 512 ? 512 : t);
 }
 template <int V> constexpr int time_maxr() { return V == 3 ? 8 : 16; }
 

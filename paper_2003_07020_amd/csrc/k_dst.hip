@@ -8,6 +8,7 @@
 // (Q x)_k = sqrt(2/(n+1)) (i/2) FFT_k.  P must be a power of two.
 #include <type_traits>
 
+#include "buf_io.hpp"
 #include "fft3.hpp"
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"

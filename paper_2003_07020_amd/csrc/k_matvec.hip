@@ -13,6 +13,7 @@
 //
 // Time stencil (rows of C, eq. (2.12)): level 0: v_0; level 1: 3/2 v_1 - 2 v_0;
 // level k >= 2: 3/2 v_k - 2 v_{k-1} + 1/2 v_{k-2}.
+#include "buf_io.hpp"
 #include "fft3.hpp"
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"

@@ -1,6 +1,7 @@
 // Vector kernels of the FGMRES outer iteration (FP64).  Reductions are deterministic: a fixed
 // grid writes one partial per block in a fixed order, and a single block sums the partials
 // with a fixed tree, so repeated runs are bitwise identical.
+#include "krylov.hpp"
 #include "rfde_internal.hpp"
 
 namespace rfde {
@@ -61,6 +62,109 @@ int launch_multi_dot(const Plan& p, const double* V, int nvec, const double* w, 
     RFDE_HIP(hipGetLastError());
   }
   k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out, 0);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+// ---- CGS2 in three sweeps over the basis (classical Gram-Schmidt applied twice) ----
+// Sweep A: h1 = V^T w.  Sweep B: w1 = w - V h1, and h2 = V^T w1 accumulated in the same sweep
+// (each element of w1 is formed in registers, then multiplied by the basis values just read).
+// Sweep C: w2 = w1 - V h2 and |w2|^2.  The arithmetic is that of CGS2; one sweep over V and w is
+// saved, and the host reads h1, h2 and |w2| once per Arnoldi step.
+constexpr int CGS_ACC = 16;  // dot products accumulated per sweep
+enum { CGS_DOT = 0, CGS_AXPY_DOT = 1, CGS_AXPY_NRM = 2 };
+
+// MODE CGS_DOT:      partial[v][b] = sum_i V[v][i] w[i], v < nv.
+// MODE CGS_AXPY_DOT: w[i] -= sum_{v < nall} h[v] V[v][i]; partial[v][b] = sum_i V[v][i] w[i]
+//                    (the updated w), v < nv.
+// MODE CGS_AXPY_NRM: w[i] -= sum_{v < nall} h[v] V[v][i]; partial[0][b] = sum_i w[i]^2.
+// V holds the vectors at stride n.  Elements are read in pairs (16-byte loads) with the last
+// element of an odd n done alone.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const double* __restrict__ V,
+                                             size_t n, int nall, int nv,
+                                             const double* __restrict__ h,
+                                             double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double acc[CGS_ACC];
+#pragma unroll
+  for (int v = 0; v < CGS_ACC; ++v) acc[v] = 0.0;
+  auto element = [&](size_t i, double wi) -> double {
+    if constexpr (MODE == CGS_DOT) {
+#pragma unroll
+      for (int v = 0; v < CGS_ACC; ++v)
+        if (v < nv) acc[v] = fma(V[(size_t)v * n + i], wi, acc[v]);
+    } else if constexpr (MODE == CGS_AXPY_DOT) {
+      // the first CGS_ACC basis values stay in registers for the dot products (nv <= CGS_ACC)
+      double vv[CGS_ACC];
+      double s = 0.0;
+#pragma unroll
+      for (int v = 0; v < CGS_ACC; ++v) {
+        if (v < nall) {
+          vv[v] = V[(size_t)v * n + i];
+          s = fma(h[v], vv[v], s);
+        }
+      }
+      for (int v = CGS_ACC; v < nall; ++v) s = fma(h[v], V[(size_t)v * n + i], s);
+      wi -= s;
+#pragma unroll
+      for (int v = 0; v < CGS_ACC; ++v)
+        if (v < nv) acc[v] = fma(vv[v], wi, acc[v]);
+    } else {
+      double s = 0.0;
+      for (int v = 0; v < nall; ++v) s = fma(h[v], V[(size_t)v * n + i], s);
+      wi -= s;
+      acc[0] = fma(wi, wi, acc[0]);
+    }
+    return wi;
+  };
+  const size_t n2 = n / 2;
+  for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < n2; k += (size_t)RED_BLOCKS * 256) {
+    const double2 wv = reinterpret_cast<const double2*>(w)[k];
+    const double a = element(2 * k, wv.x), b = element(2 * k + 1, wv.y);
+    if constexpr (MODE != CGS_DOT) reinterpret_cast<double2*>(w)[k] = make_double2(a, b);
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double a = element(n - 1, w[n - 1]);
+    if constexpr (MODE != CGS_DOT) w[n - 1] = a;
+  }
+  const int nout = MODE == CGS_AXPY_NRM ? 1 : nv;
+#pragma unroll
+  for (int v = 0; v < CGS_ACC; ++v) {
+    if (v < nout) {
+      const double s = block_sum_256(acc[v], sh);
+      if (threadIdx.x == 0) partial[v * RED_BLOCKS + blockIdx.x] = s;
+    }
+  }
+}
+
+int launch_cgs2(const Plan& p, const double* V, int nvec, double* w, double* out) {
+  const size_t n = p.N();
+  // sweep A: h1 -> out[0 .. nvec)
+  for (int v0 = 0; v0 < nvec; v0 += CGS_ACC) {
+    k_cgs<CGS_DOT><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V + (size_t)v0 * n, n, 0,
+                                                     std::min(CGS_ACC, nvec - v0), nullptr,
+                                                     p.red + (size_t)v0 * RED_BLOCKS);
+    RFDE_HIP(hipGetLastError());
+  }
+  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out, 0);
+  RFDE_HIP(hipGetLastError());
+  // sweep B: w -= V h1; h2 -> out[CGS2_H2 ..)
+  k_cgs<CGS_AXPY_DOT><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nvec, std::min(CGS_ACC, nvec),
+                                                        out, p.red);
+  RFDE_HIP(hipGetLastError());
+  for (int v0 = CGS_ACC; v0 < nvec; v0 += CGS_ACC) {
+    k_cgs<CGS_DOT><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V + (size_t)v0 * n, n, 0,
+                                                     std::min(CGS_ACC, nvec - v0), nullptr,
+                                                     p.red + (size_t)v0 * RED_BLOCKS);
+    RFDE_HIP(hipGetLastError());
+  }
+  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out + CGS2_H2, 0);
+  RFDE_HIP(hipGetLastError());
+  // sweep C: w -= V h2; |w| -> out[CGS2_NRM]
+  k_cgs<CGS_AXPY_NRM><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nvec, 1, out + CGS2_H2, p.red);
+  RFDE_HIP(hipGetLastError());
+  k_dot_final<<<1, 256, 0, p.stream>>>(p.red, out + CGS2_NRM, 1);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

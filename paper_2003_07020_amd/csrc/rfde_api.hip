@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "krylov.hpp"
 #include "rfde_internal.hpp"
 
 namespace rfde {
@@ -519,17 +520,11 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
       RFDE_TRY(apply_pinv(p, vj, zj));
       RFDE_HIP(hipEventRecord(p.ev[1], st));
       RFDE_TRY(timed_matvec(zj, vn));
-      // classical Gram-Schmidt, twice (CGS2)
-      RFDE_TRY(launch_multi_dot(p, p.vbuf, j + 1, vn, p.redout));
-      RFDE_TRY(launch_multi_axpy(p, vn, p.vbuf, j + 1, p.redout, -1.0));
-      RFDE_TRY(fetch(j + 1));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hr[i];
-      RFDE_TRY(launch_multi_dot(p, p.vbuf, j + 1, vn, p.redout));
-      RFDE_TRY(launch_multi_axpy(p, vn, p.vbuf, j + 1, p.redout, -1.0));
-      RFDE_TRY(launch_nrm2(p, vn, p.redout + j + 1));
-      RFDE_TRY(fetch(j + 2));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hr[i];
-      const double hn = hr[j + 1];
+      // classical Gram-Schmidt, twice (CGS2), in three sweeps; one read-back per step
+      RFDE_TRY(launch_cgs2(p, p.vbuf, j + 1, vn, p.redout));
+      RFDE_TRY(fetch(CGS2_NRM + 1));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hr[i] + hr[CGS2_H2 + i];
+      const double hn = hr[CGS2_NRM];
       {
         float t;
         RFDE_HIP(hipEventElapsedTime(&t, p.ev[0], p.ev[1]));
@@ -538,7 +533,7 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
       }
       if (!std::isfinite(hn)) return RFDE_ENAN;
       H[(size_t)(j + 1) * m + j] = hn;
-      if (hn > 0.0) RFDE_TRY(launch_scale_copy(p, vn, vn, p.redout + j + 1, 1));
+      if (hn > 0.0) RFDE_TRY(launch_scale_copy(p, vn, vn, p.redout + CGS2_NRM, 1));
       else breakdown = true;
       // apply previous rotations, then a new one
       for (int i = 0; i < j; ++i) {

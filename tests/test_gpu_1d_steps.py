@@ -95,6 +95,19 @@ def test_rhs_and_matvec(alpha, kappa, M, Nt):
     assert rel_max(y, aa.apply_all_at_once(v, A, tau)) < TOL_FFT
 
 
+@pytest.mark.parametrize("alpha,M,Nt", [(1.6, 500, 5), (1.4, 1000, 3), (1.7, 2047, 2),
+                                         (1.3, 1500, 7)])
+def test_matvec_register_fft_lengths(alpha, M, Nt):
+    # the three-stage register FFT at L = 1024, 2048, 4096 (the other cases cover 256, 512 and
+    # 8192), with an odd level count (the last row pair has one row)
+    banner(f"matvec lengths alpha={alpha} M={M} Nt={Nt}")
+    p = _plan(alpha, 1.0, M, Nt)
+    h, tau, A, eps = _oracle_setup(alpha, 1.0, M, Nt)
+    v = random_vector(14, Nt * M).reshape(Nt, M)
+    y = to_host(p.apply_A(to_dev(v.ravel()))).reshape(Nt, M)
+    assert rel_max(y, aa.apply_all_at_once(v, A, tau)) < TOL_FFT
+
+
 @pytest.mark.parametrize("alpha,kappa,M,Nt", CASES)
 def test_preconditioner_steps(alpha, kappa, M, Nt):
     banner(f"pinv steps alpha={alpha} M={M} Nt={Nt}")

@@ -17,6 +17,7 @@ CASES = [  # (alpha_x, alpha_y, Mx, My, Nt)
     (1.5, 1.5, 31, 31, 16),
     (1.7, 1.9, 63, 15, 4),
     (1.2, 1.8, 7, 127, 2),
+    (1.5, 1.3, 255, 7, 3),  # x rows on the register FFT (L = 512), odd row count
 ]
 
 

@@ -85,7 +85,6 @@ __global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const doubl
                                              size_t n, int nall, int nv,
                                              const double* __restrict__ h,
                                              double* __restrict__ partial) {
-  __shared__ double sh[4];
   double acc[CGS_ACC];
 #pragma unroll
   for (int v = 0; v < CGS_ACC; ++v) acc[v] = 0.0;
@@ -128,13 +127,23 @@ __global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const doubl
     const double a = element(n - 1, w[n - 1]);
     if constexpr (MODE != CGS_DOT) w[n - 1] = a;
   }
+  // per-wave sums of every accumulator, then one barrier and the four wave sums per value in
+  // the fixed order (w0 + w1) + (w2 + w3)
   const int nout = MODE == CGS_AXPY_NRM ? 1 : nv;
+  __shared__ double shv[4][CGS_ACC];
 #pragma unroll
   for (int v = 0; v < CGS_ACC; ++v) {
     if (v < nout) {
-      const double s = block_sum_256(acc[v], sh);
-      if (threadIdx.x == 0) partial[v * RED_BLOCKS + blockIdx.x] = s;
+      double r = acc[v];
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) r += __shfl_xor(r, m);
+      if ((threadIdx.x & 63) == 0) shv[threadIdx.x >> 6][v] = r;
     }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nout) {
+    const int v = threadIdx.x;
+    partial[v * RED_BLOCKS + blockIdx.x] = (shv[0][v] + shv[1][v]) + (shv[2][v] + shv[3][v]);
   }
 }
 

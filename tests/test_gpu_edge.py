@@ -41,6 +41,23 @@ def test_bc_preconditioner_eps_one():
     assert st1.iters >= st.iters
 
 
+def test_long_arnoldi_cycle():
+    # more than 16 Arnoldi steps in one restart cycle: the Gram-Schmidt sweeps then split the
+    # basis into chunks of 16 dot products (tau step (b), which is inexact, at tight tolerances)
+    banner("long Arnoldi cycle")
+    iters = []
+    for alpha, M, Nt, tol, bits in ((1.05, 1023, 16, 1e-13, 64), (1.1, 511, 64, 1e-12, 32)):
+        p = _plan(alpha, 1.0, M, Nt, tol=tol, spatial="tau", precond_bits=bits, restart=40)
+        h, tau = aa.mesh(0.0, 1.0, M, 1.0, Nt)
+        u0, f, _ = gen1d(21, M, Nt)
+        U, st, _ = p.solve(to_dev(u0), to_dev(f.ravel()))
+        Uref = aa.bdf2_march(u0, f, aa.jacobian_A(alpha, 1.0, h, M), tau)
+        assert st.converged and st.true_rel_res <= tol
+        assert rel_max(to_host(U).reshape(Nt, M), Uref) < 1e-9
+        iters.append(st.iters)
+    assert max(iters) > 16, iters
+
+
 def test_tiny_kappa_and_single_point():
     banner("kappa tiny, M=1")
     _check_solve(1.5, 1e-6, 31, 8)

@@ -78,42 +78,52 @@ enum { CGS_DOT = 0, CGS_AXPY_DOT = 1, CGS_AXPY_NRM = 2 };
 // MODE CGS_AXPY_DOT: w[i] -= sum_{v < nall} h[v] V[v][i]; partial[v][b] = sum_i V[v][i] w[i]
 //                    (the updated w), v < nv.
 // MODE CGS_AXPY_NRM: w[i] -= sum_{v < nall} h[v] V[v][i]; partial[0][b] = sum_i w[i]^2.
-// V holds the vectors at stride n.  Elements are read in pairs (16-byte loads) with the last
-// element of an odd n done alone.
-template <int MODE>
+// V holds the vectors at stride n.  NV > 0: nv = NV and, for the correcting modes, nall = NV,
+// known at compile time so every basis value of an element is loaded before any is used (all
+// loads in flight together); NV = 0: any nall (> CGS_ACC) with nv = CGS_ACC, by loops.
+// Elements are read in pairs (16-byte loads) with the last element of an odd n done alone.
+template <int MODE, int NV>
 __global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const double* __restrict__ V,
-                                             size_t n, int nall, int nv,
-                                             const double* __restrict__ h,
+                                             size_t n, int nall, const double* __restrict__ h,
                                              double* __restrict__ partial) {
-  double acc[CGS_ACC];
+  constexpr int NACC = MODE == CGS_AXPY_NRM ? 1 : (NV > 0 ? NV : CGS_ACC);
+  double acc[NACC];
 #pragma unroll
-  for (int v = 0; v < CGS_ACC; ++v) acc[v] = 0.0;
+  for (int v = 0; v < NACC; ++v) acc[v] = 0.0;
   auto element = [&](size_t i, double wi) -> double {
-    if constexpr (MODE == CGS_DOT) {
+    if constexpr (NV > 0) {
+      double vv[NV];
 #pragma unroll
-      for (int v = 0; v < CGS_ACC; ++v)
-        if (v < nv) acc[v] = fma(V[(size_t)v * n + i], wi, acc[v]);
-    } else if constexpr (MODE == CGS_AXPY_DOT) {
-      // the first CGS_ACC basis values stay in registers for the dot products (nv <= CGS_ACC)
+      for (int v = 0; v < NV; ++v) vv[v] = V[(size_t)v * n + i];
+      if constexpr (MODE != CGS_DOT) {
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s = fma(h[v], vv[v], s);
+        wi -= s;
+      }
+      if constexpr (MODE == CGS_AXPY_NRM) {
+        acc[0] = fma(wi, wi, acc[0]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = fma(vv[v], wi, acc[v]);
+      }
+    } else {
+      static_assert(MODE != CGS_DOT, "dot sweeps take at most CGS_ACC vectors per launch");
       double vv[CGS_ACC];
       double s = 0.0;
 #pragma unroll
       for (int v = 0; v < CGS_ACC; ++v) {
-        if (v < nall) {
-          vv[v] = V[(size_t)v * n + i];
-          s = fma(h[v], vv[v], s);
-        }
+        vv[v] = V[(size_t)v * n + i];
+        s = fma(h[v], vv[v], s);
       }
       for (int v = CGS_ACC; v < nall; ++v) s = fma(h[v], V[(size_t)v * n + i], s);
       wi -= s;
+      if constexpr (MODE == CGS_AXPY_NRM) {
+        acc[0] = fma(wi, wi, acc[0]);
+      } else {
 #pragma unroll
-      for (int v = 0; v < CGS_ACC; ++v)
-        if (v < nv) acc[v] = fma(vv[v], wi, acc[v]);
-    } else {
-      double s = 0.0;
-      for (int v = 0; v < nall; ++v) s = fma(h[v], V[(size_t)v * n + i], s);
-      wi -= s;
-      acc[0] = fma(wi, wi, acc[0]);
+        for (int v = 0; v < CGS_ACC; ++v) acc[v] = fma(vv[v], wi, acc[v]);
+      }
     }
     return wi;
   };
@@ -129,50 +139,70 @@ __global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const doubl
   }
   // per-wave sums of every accumulator, then one barrier and the four wave sums per value in
   // the fixed order (w0 + w1) + (w2 + w3)
-  const int nout = MODE == CGS_AXPY_NRM ? 1 : nv;
-  __shared__ double shv[4][CGS_ACC];
+  __shared__ double shv[4][NACC];
 #pragma unroll
-  for (int v = 0; v < CGS_ACC; ++v) {
-    if (v < nout) {
-      double r = acc[v];
+  for (int v = 0; v < NACC; ++v) {
+    double r = acc[v];
 #pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) r += __shfl_xor(r, m);
-      if ((threadIdx.x & 63) == 0) shv[threadIdx.x >> 6][v] = r;
-    }
+    for (int m = 32; m >= 1; m >>= 1) r += __shfl_xor(r, m);
+    if ((threadIdx.x & 63) == 0) shv[threadIdx.x >> 6][v] = r;
   }
   __syncthreads();
-  if ((int)threadIdx.x < nout) {
+  if ((int)threadIdx.x < NACC) {
     const int v = threadIdx.x;
     partial[v * RED_BLOCKS + blockIdx.x] = (shv[0][v] + shv[1][v]) + (shv[2][v] + shv[3][v]);
   }
+}
+
+// launch of mode MODE over nv (1..CGS_ACC) vectors known at compile time, or NV = 0
+template <int MODE>
+static int cgs_launch(const Plan& p, double* w, const double* V, int nall, int nv,
+                      const double* h, double* partial) {
+  const size_t n = p.N();
+#define RFDE_CGS_CASE(K)                                                                     \
+  case K:                                                                                    \
+    k_cgs<MODE, K><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nall, h, partial);             \
+    break;
+  if (MODE != CGS_DOT && nall > CGS_ACC) {
+    if constexpr (MODE != CGS_DOT)
+      k_cgs<MODE, 0><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nall, h, partial);
+  } else {
+    switch (nv) {
+      RFDE_CGS_CASE(1) RFDE_CGS_CASE(2) RFDE_CGS_CASE(3) RFDE_CGS_CASE(4)
+      RFDE_CGS_CASE(5) RFDE_CGS_CASE(6) RFDE_CGS_CASE(7) RFDE_CGS_CASE(8)
+      RFDE_CGS_CASE(9) RFDE_CGS_CASE(10) RFDE_CGS_CASE(11) RFDE_CGS_CASE(12)
+      RFDE_CGS_CASE(13) RFDE_CGS_CASE(14) RFDE_CGS_CASE(15) RFDE_CGS_CASE(16)
+      default: return RFDE_EINVAL;
+    }
+  }
+#undef RFDE_CGS_CASE
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
 }
 
 int launch_cgs2(const Plan& p, const double* V, int nvec, double* w, double* out) {
   const size_t n = p.N();
   // sweep A: h1 -> out[0 .. nvec)
   for (int v0 = 0; v0 < nvec; v0 += CGS_ACC) {
-    k_cgs<CGS_DOT><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V + (size_t)v0 * n, n, 0,
-                                                     std::min(CGS_ACC, nvec - v0), nullptr,
-                                                     p.red + (size_t)v0 * RED_BLOCKS);
-    RFDE_HIP(hipGetLastError());
+    const int nv = std::min(CGS_ACC, nvec - v0);
+    RFDE_TRY(cgs_launch<CGS_DOT>(p, w, V + (size_t)v0 * n, nv, nv, nullptr,
+                                 p.red + (size_t)v0 * RED_BLOCKS));
   }
   k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out, 0);
   RFDE_HIP(hipGetLastError());
-  // sweep B: w -= V h1; h2 -> out[CGS2_H2 ..)
-  k_cgs<CGS_AXPY_DOT><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nvec, std::min(CGS_ACC, nvec),
-                                                        out, p.red);
-  RFDE_HIP(hipGetLastError());
+  // sweep B: w -= V h1 and the dot products with the first CGS_ACC vectors; the rest (if any)
+  // by dot sweeps; h2 -> out[CGS2_H2 ..)
+  RFDE_TRY(cgs_launch<CGS_AXPY_DOT>(p, w, V, nvec, std::min(CGS_ACC, nvec), out, p.red));
   for (int v0 = CGS_ACC; v0 < nvec; v0 += CGS_ACC) {
-    k_cgs<CGS_DOT><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V + (size_t)v0 * n, n, 0,
-                                                     std::min(CGS_ACC, nvec - v0), nullptr,
-                                                     p.red + (size_t)v0 * RED_BLOCKS);
-    RFDE_HIP(hipGetLastError());
+    const int nv = std::min(CGS_ACC, nvec - v0);
+    RFDE_TRY(cgs_launch<CGS_DOT>(p, w, V + (size_t)v0 * n, nv, nv, nullptr,
+                                 p.red + (size_t)v0 * RED_BLOCKS));
   }
   k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out + CGS2_H2, 0);
   RFDE_HIP(hipGetLastError());
-  // sweep C: w -= V h2; |w| -> out[CGS2_NRM]
-  k_cgs<CGS_AXPY_NRM><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nvec, 1, out + CGS2_H2, p.red);
-  RFDE_HIP(hipGetLastError());
+  // sweep C: w -= V h2 and |w| -> out[CGS2_NRM]
+  RFDE_TRY(cgs_launch<CGS_AXPY_NRM>(p, w, V, nvec, std::min(CGS_ACC, nvec), out + CGS2_H2,
+                                    p.red));
   k_dot_final<<<1, 256, 0, p.stream>>>(p.red, out + CGS2_NRM, 1);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;

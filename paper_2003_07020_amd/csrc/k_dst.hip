@@ -26,7 +26,7 @@ __device__ __forceinline__ C dst_coef(C y, typename cplx_traits<C>::real sc) {
 // SCALE, divide coefficient k by (lambda_f + coef sigma_k) and apply the DST again
 // (f = row / rows_per_freq).  The odd extension is formed by the first FFT pass's loads and the
 // coefficients are written by the last pass's stores.
-template <int P, int NB, int NT, typename C, bool SCALE>
+template <int P, int NB, int NT, typename C, bool SCALE, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_dst_rows(C* __restrict__ z, int nrows, int rows_per_freq,
                                                  const double2* __restrict__ lambda,
                                                  const double* __restrict__ sigma, double coef,
@@ -65,12 +65,12 @@ __global__ void __launch_bounds__(NT) k_dst_rows(C* __restrict__ z, int nrows, i
         B[P - idx] = cmk<C>(-wv.x, -wv.y);
       }
     };
-    fft_io<P, -1, NT, NB, P, false, true, true>(buf, tw, load, store_scaled);
+    fft_io<P, -1, NT, NB, P, false, true, true, MAXR>(buf, tw, load, store_scaled);
     __syncthreads();
     NoLoad nl;
-    fft_io<P, -1, NT, NB, P, false, false, true>(buf, tw, nl, store_out);
+    fft_io<P, -1, NT, NB, P, false, false, true, MAXR>(buf, tw, nl, store_out);
   } else {
-    fft_io<P, -1, NT, NB, P, false, true, true>(buf, tw, load, store_out);
+    fft_io<P, -1, NT, NB, P, false, true, true, MAXR>(buf, tw, load, store_out);
   }
 }
 
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256, WAVES) k_dst3_scale(const C* zin, C* zout
 // Columns of [nf][My][Mx] planes: one block per (frequency, tile of NB columns), columns taken
 // fastest by the threads.  DST along y, divide by lambda_n + coef_x sigma^x_ix +
 // coef_y sigma^y_iy (the x-direction DST has already been applied to the rows), DST again.
-template <int P, int NB, int NT, typename C>
+template <int P, int NB, int NT, typename C, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_dst_cols(C* __restrict__ z, int Mx,
                                                  const double2* __restrict__ lambda,
                                                  const double* __restrict__ sigx,
@@ -202,14 +202,14 @@ __global__ void __launch_bounds__(NT) k_dst_cols(C* __restrict__ z, int Mx,
       B[P - idx] = cmk<C>(-wv.x, -wv.y);
     }
   };
-  fft_io<P, -1, NT, NB, LDN, true, true, true>(buf, tw, load, store_scaled);
+  fft_io<P, -1, NT, NB, LDN, true, true, true, MAXR>(buf, tw, load, store_scaled);
   __syncthreads();
   auto store_out = [&](int b, int idx, C y) {
     const int x = x0 + b;
     if (x < Mx && idx >= 1 && idx <= n) plane[(size_t)(idx - 1) * Mx + x] = dst_coef(y, sc);
   };
   NoLoad nl;
-  fft_io<P, -1, NT, NB, LDN, true, false, true>(buf, tw, nl, store_out);
+  fft_io<P, -1, NT, NB, LDN, true, false, true, MAXR>(buf, tw, nl, store_out);
 }
 
 template <int P, typename C>
@@ -218,10 +218,13 @@ constexpr int dst_nb() {
   constexpr int cap = 135168 / ((P + 1) * (int)sizeof(C));
   return cap < 1 ? 1 : (cap < target ? cap : target);
 }
-// one radix-16 butterfly per thread (NB P / 16, between 64 and 512)
+// Largest radix: 8 up to P = 512 (twice the threads of radix 16 for the same LDS, so more waves
+// per CU hide the global-memory latency of these short transforms), 16 above.
+template <int P> constexpr int dst_maxr() { return P <= 512 ? 8 : 16; }
+// one largest-radix butterfly per thread (NB P / MAXR, between 64 and 512)
 template <int P, typename C>
 constexpr int dst_nt() {
-  constexpr int t = dst_nb<P, C>() * P / 16;
+  constexpr int t = dst_nb<P, C>() * P / dst_maxr<P>();
   return t < 64 ? 64 : (t > 512 ? 512 : t);
 }
 
@@ -250,7 +253,7 @@ static int dst_rows(const Plan& p, C* z, int nrows, int rows_per_freq, const dou
                     double coef, const C* tw) {
   constexpr int NB = dst_nb<P, C>();
   constexpr int NT = dst_nt<P, C>();
-  k_dst_rows<P, NB, NT, C, SCALE><<<(nrows + NB - 1) / NB, NT, 0, p.stream>>>(
+  k_dst_rows<P, NB, NT, C, SCALE, dst_maxr<P>()><<<(nrows + NB - 1) / NB, NT, 0, p.stream>>>(
       z, nrows, rows_per_freq, p.lambda, sigma, coef, tw);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
@@ -261,7 +264,7 @@ static int dst_cols(const Plan& p, C* z, const C* tw) {
   constexpr int NB = dst_nb<P, C>();
   constexpr int NT = dst_nt<P, C>();
   const int ntile = (p.Mx + NB - 1) / NB;
-  k_dst_cols<P, NB, NT, C><<<p.nf * ntile, NT, 0, p.stream>>>(z, p.Mx, p.lambda, p.sigma,
+  k_dst_cols<P, NB, NT, C, dst_maxr<P>()><<<p.nf * ntile, NT, 0, p.stream>>>(z, p.Mx, p.lambda, p.sigma,
                                                               p.sigma + p.Mx, p.coef_x, p.coef_y,
                                                               tw);
   RFDE_HIP(hipGetLastError());

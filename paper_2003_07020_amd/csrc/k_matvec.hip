@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(256, WAVES)
 // 2D, y direction: for one time level and a tile of 2*NB adjacent columns, NB complex transforms
 // of length L along y (column pairs packed as real/imaginary parts, batch index fastest so the
 // row segments are read and written contiguously).  Adds (tau c_y T_y along y) v into y.
-template <int L, int NB, int NT>
+template <int L, int NB, int NT, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_matvec_2d_y(const double* __restrict__ v,
                                                     double* __restrict__ y,
                                                     const double* __restrict__ sym,
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(NT) k_matvec_2d_y(const double* __restrict__ v
     const double s = sym[idx <= L / 2 ? idx : L - idx];
     buf[f * LDN + idx] = make_double2(c.x * s, c.y * s);
   };
-  fft_io<L, -1, NT, NB, LDN, true, true, true>(buf, tw, load, store_scaled);
+  fft_io<L, -1, NT, NB, LDN, true, true, true, MAXR>(buf, tw, load, store_scaled);
   __syncthreads();
   auto store_out = [&](int f, int iy, double2 c) {
     const int x = x0 + 2 * f;
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(NT) k_matvec_2d_y(const double* __restrict__ v
     }
   };
   NoLoad nl;
-  fft_io<L, +1, NT, NB, LDN, true, false, true>(buf, tw, nl, store_out);
+  fft_io<L, +1, NT, NB, LDN, true, false, true, MAXR>(buf, tw, nl, store_out);
 }
 
 // Variants: 0 = three-stage register FFT (L >= 256; smaller L: the Stockham kernel);
@@ -248,11 +248,13 @@ template <int L>
 static int mv2dy(const Plan& p, const double* v, double* y) {
   // tile of 2*NB columns: 128-byte row segments where the LDS budget (~130 KB) allows
   constexpr int NB = (8 * (L + 1) * 16 <= 135168) ? 8 : ((4 * (L + 1) * 16 <= 135168) ? 4 : ((2 * (L + 1) * 16 <= 135168) ? 2 : 1));
-  constexpr int NT = (NB * L / 16 < 64) ? 64 : (NB * L / 16 > 512 ? 512 : NB * L / 16);
+  // radix 8 up to L = 512 (twice the threads per LDS byte: more waves to hide latency)
+  constexpr int MAXR = L <= 512 ? 8 : 16;
+  constexpr int NT = (NB * L / MAXR < 64) ? 64 : (NB * L / MAXR > 512 ? 512 : NB * L / MAXR);
   const int ntile = (p.Mx + 2 * NB - 1) / (2 * NB);
   const double* symy = p.sym + (p.Lx / 2 + 1);
   const double2* twy = p.twL + p.Lx;
-  k_matvec_2d_y<L, NB, NT><<<p.Nt * ntile, NT, 0, p.stream>>>(v, y, symy, twy, p.Mx, p.My);
+  k_matvec_2d_y<L, NB, NT, MAXR><<<p.Nt * ntile, NT, 0, p.stream>>>(v, y, symy, twy, p.Mx, p.My);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

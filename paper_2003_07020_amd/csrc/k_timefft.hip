@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(NT) k_time_inv(const C* __restrict__ z2, doubl
 }
 
 // ---- Bluestein variants (Nt not a power of two, LB = Lt) ----
-template <int LB, int NB, int NT, typename C>
+template <int LB, int NB, int NT, typename C, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_time_fwd_bs(const double* __restrict__ v, C* __restrict__ z1,
                                                     const double* __restrict__ s,
                                                     const C* __restrict__ tw,
@@ -114,13 +114,13 @@ __global__ void __launch_bounds__(NT) k_time_fwd_bs(const double* __restrict__ v
   };
   NoLoad nl;
   NoStore ns;
-  fft_io<LB, -1, NT, NB, LDN, true, true, false>(buf, tw, load, ns);
+  fft_io<LB, -1, NT, NB, LDN, true, true, false, MAXR>(buf, tw, load, ns);
   for (int e = threadIdx.x; e < NB * LB; e += NT) {
     const int f = e % NB, k = e / NB;
     buf[f * LDN + k] = cmul(buf[f * LDN + k], bhat[k]);
   }
   __syncthreads();
-  fft_io<LB, +1, NT, NB, LDN, true, false, false>(buf, tw, nl, ns);
+  fft_io<LB, +1, NT, NB, LDN, true, false, false, MAXR>(buf, tw, nl, ns);
   const int nf = Nt / 2 + 1;
   for (int e = threadIdx.x; e < nf * TS; e += NT) {
     const int n = e / TS, q = e - n * TS;
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(NT) k_time_fwd_bs(const double* __restrict__ v
   }
 }
 
-template <int LB, int NB, int NT, typename C>
+template <int LB, int NB, int NT, typename C, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_time_inv_bs(const C* __restrict__ z2, double* __restrict__ v,
                                                     const double* __restrict__ s,
                                                     const C* __restrict__ tw,
@@ -174,14 +174,14 @@ __global__ void __launch_bounds__(NT) k_time_inv_bs(const C* __restrict__ z2, do
     if (i + 1 < S) row[i + 1] = -(double)Rj.y * sc;
   };
   NoStore ns;
-  fft_io<LB, -1, NT, NB, LDN, true, true, false>(buf, tw, load, ns);
+  fft_io<LB, -1, NT, NB, LDN, true, true, false, MAXR>(buf, tw, load, ns);
   for (int e = threadIdx.x; e < NB * LB; e += NT) {
     const int f = e % NB, k = e / NB;
     buf[f * LDN + k] = cmul(buf[f * LDN + k], bhat[k]);
   }
   __syncthreads();
   NoLoad nl;
-  fft_io<LB, +1, NT, NB, LDN, true, false, true>(buf, tw, nl, store);
+  fft_io<LB, +1, NT, NB, LDN, true, false, true, MAXR>(buf, tw, nl, store);
 }
 
 // w_k = exp(i pi (k^2 mod 2 Nt) / Nt) in both precisions (the integer reduction keeps the
@@ -230,22 +230,24 @@ constexpr int time_nb() {
   constexpr int sh = V == 3 ? 0 : V;
   return (nb >> sh) < 1 ? 1 : (nb >> sh);
 }
-// Threads: one radix-16 butterfly each (NB N / 16, between 64 and 512); variant 3: 1024 threads
-// for NB N >= 8192.
+// Largest radix: 8 for variant 3 and for N <= 512 (twice the threads of radix 16 for the same
+// LDS, so more waves per CU hide the global-memory latency of these short transforms), else 16.
+template <int N, int V> constexpr int time_maxr() { return (V == 3 || N <= 512) ? 8 : 16; }
+// Threads: one largest-radix butterfly each (NB N / MAXR, between 64 and 512); variant 3: 1024
+// threads for NB N >= 8192.
 template <int N, typename C, int V = 0>
 constexpr int time_nt() {
-  if (V == 3) return time_nb<N, C, V>() * N >= 8192 ? 1024 : 256;
-  constexpr int t = time_nb<N, C, V>() * N / 16;
+  if (V == 3 && time_nb<N, C, V>() * N >= 8192) return 1024;
+  constexpr int t = time_nb<N, C, V>() * N / time_maxr<N, V>();
   return t < 64 ? 64 : (t > 512 ? 512 : t);
 }
-template <int V> constexpr int time_maxr() { return V == 3 ? 8 : 16; }
 
 template <int N, typename C, int V>
 static int tf_fwd_v(const Plan& p, const double* v, void* z1, const C* tw) {
   constexpr int NB = time_nb<N, C, V>();
   constexpr int NT = time_nt<N, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_fwd<N, NB, NT, C, time_maxr<V>()><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S,
+  k_time_fwd<N, NB, NT, C, time_maxr<N, V>()><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S,
                                                                          p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
@@ -255,7 +257,7 @@ static int tf_inv_v(const Plan& p, const void* z2, double* v, const C* tw) {
   constexpr int NB = time_nb<N, C, V>();
   constexpr int NT = time_nt<N, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_inv<N, NB, NT, C, time_maxr<V>()><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw,
+  k_time_inv<N, NB, NT, C, time_maxr<N, V>()><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw,
                                                                          p.S, p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
@@ -281,7 +283,7 @@ static int tf_fwd_bs_v(const Plan& p, const double* v, void* z1, const C* tw, co
   constexpr int NB = time_nb<LB, C, V>();
   constexpr int NT = time_nt<LB, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_fwd_bs<LB, NB, NT, C><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, w, bh, p.S, p.Nt,
+  k_time_fwd_bs<LB, NB, NT, C, time_maxr<LB, V>()><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, w, bh, p.S, p.Nt,
                                                             p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
@@ -292,7 +294,7 @@ static int tf_inv_bs_v(const Plan& p, const void* z2, double* v, const C* tw, co
   constexpr int NB = time_nb<LB, C, V>();
   constexpr int NT = time_nt<LB, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_inv_bs<LB, NB, NT, C><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw, w, bh, p.S,
+  k_time_inv_bs<LB, NB, NT, C, time_maxr<LB, V>()><<<blocks, NT, 0, p.stream>>>((const C*)z2, v, p.s, tw, w, bh, p.S,
                                                              p.Nt, p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;

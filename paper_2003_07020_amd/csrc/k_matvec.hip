@@ -201,12 +201,14 @@ static int mv_rows(const Plan& p, const double* v, double* y, int n, int rows, i
   using E = Fft3For<L, 256>;
   // L = 8192 needs more than 256 registers per lane at one wave per SIMD; bounding it to two
   // waves costs a few spills but hides latency better (measured 35 vs 44 us at M = 4095).
-  constexpr int WAVES = L >= 8192 ? 2 : 1;
+  // L <= 512 fits four waves (128 registers) without spills.
+  constexpr int WAVES = L >= 8192 ? 2 : (L <= 512 ? 4 : 1);
   const int groups = ((rows + 1) / 2 + E::NB - 1) / E::NB;
   if (rpl == 1)
     k_matvec3<L, true, WAVES><<<groups, 256, 0, p.stream>>>(v, y, p.sym, p.twL, n, rows, 1, live);
   else
-    k_matvec3<L, false, 1><<<groups, 256, 0, p.stream>>>(v, y, p.sym, p.twL, n, rows, rpl, live);
+    k_matvec3<L, false, WAVES><<<groups, 256, 0, p.stream>>>(v, y, p.sym, p.twL, n, rows, rpl,
+                                                            live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

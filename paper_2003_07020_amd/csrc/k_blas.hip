@@ -217,13 +217,25 @@ int launch_nrm2(const Plan& p, const double* x, double* out) {
   return RFDE_OK;
 }
 
-// w[i] += sign * sum_v coef[v] V[v][i]
-__global__ void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, size_t n,
-                             int nvec, const double* __restrict__ coef, double sign) {
+// w[i] += sign * sum_v coef[v] V[v][i]; NV > 0: nvec = NV known at compile time (all loads of an
+// element in flight together), NV = 0: any nvec by a loop.
+template <int NV>
+__global__ void __launch_bounds__(256) k_multi_axpy(double* __restrict__ w,
+                                                   const double* __restrict__ V, size_t n,
+                                                   int nvec, const double* __restrict__ coef,
+                                                   double sign) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int v = 0; v < nvec; ++v) s = fma(coef[v], V[v * n + i], s);
+    if constexpr (NV > 0) {
+      double vv[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) vv[v] = V[(size_t)v * n + i];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s = fma(coef[v], vv[v], s);
+    } else {
+      for (int v = 0; v < nvec; ++v) s = fma(coef[v], V[(size_t)v * n + i], s);
+    }
     w[i] = fma(sign, s, w[i]);
   }
 }
@@ -232,7 +244,18 @@ int launch_multi_axpy(const Plan& p, double* w, const double* V, int nvec, const
                       double sign) {
   const size_t n = p.N();
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
-  k_multi_axpy<<<blocks, 256, 0, p.stream>>>(w, V, n, nvec, coef, sign);
+#define RFDE_AXPY_CASE(K)                                                                    \
+  case K:                                                                                    \
+    k_multi_axpy<K><<<blocks, 256, 0, p.stream>>>(w, V, n, nvec, coef, sign);                \
+    break;
+  switch (nvec) {
+    RFDE_AXPY_CASE(1) RFDE_AXPY_CASE(2) RFDE_AXPY_CASE(3) RFDE_AXPY_CASE(4)
+    RFDE_AXPY_CASE(5) RFDE_AXPY_CASE(6) RFDE_AXPY_CASE(7) RFDE_AXPY_CASE(8)
+    RFDE_AXPY_CASE(9) RFDE_AXPY_CASE(10) RFDE_AXPY_CASE(11) RFDE_AXPY_CASE(12)
+    RFDE_AXPY_CASE(13) RFDE_AXPY_CASE(14) RFDE_AXPY_CASE(15) RFDE_AXPY_CASE(16)
+    default: k_multi_axpy<0><<<blocks, 256, 0, p.stream>>>(w, V, n, nvec, coef, sign);
+  }
+#undef RFDE_AXPY_CASE
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

@@ -262,16 +262,38 @@ static int tf_inv_v(const Plan& p, const void* z2, double* v, const C* tw) {
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
+// Compute units of the plan's device (queried once per device).
+static int device_cus(int dev) {
+  static int cached[64] = {0};
+  if (dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        c <= 0)
+      return 256;
+    cached[dev] = c;
+  }
+  return cached[dev];
+}
+// Variant 0 takes the half-width shape (variant 1) when the full width would leave CUs without
+// a workgroup (e.g. complex64 at 32 columns per workgroup: 128 workgroups for 4095 columns).
+template <int N, typename C>
+static bool time_narrow(const Plan& p) {
+  constexpr int NB = time_nb<N, C, 0>();
+  return NB >= 2 && (p.S + 2 * NB - 1) / (2 * NB) < device_cus(p.device);
+}
 template <int N, typename C>
 static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw) {
-  if (p.tv_time == 1) return tf_fwd_v<N, C, 1>(p, v, z1, tw);
+  if (p.tv_time == 1 || (p.tv_time == 0 && time_narrow<N, C>(p)))
+    return tf_fwd_v<N, C, 1>(p, v, z1, tw);
   if (p.tv_time == 2) return tf_fwd_v<N, C, 2>(p, v, z1, tw);
   if (p.tv_time == 3) return tf_fwd_v<N, C, 3>(p, v, z1, tw);
   return tf_fwd_v<N, C, 0>(p, v, z1, tw);
 }
 template <int N, typename C>
 static int tf_inv(const Plan& p, const void* z2, double* v, const C* tw) {
-  if (p.tv_time == 1) return tf_inv_v<N, C, 1>(p, z2, v, tw);
+  if (p.tv_time == 1 || (p.tv_time == 0 && time_narrow<N, C>(p)))
+    return tf_inv_v<N, C, 1>(p, z2, v, tw);
   if (p.tv_time == 2) return tf_inv_v<N, C, 2>(p, z2, v, tw);
   if (p.tv_time == 3) return tf_inv_v<N, C, 3>(p, z2, v, tw);
   return tf_inv_v<N, C, 0>(p, z2, v, tw);

@@ -19,6 +19,14 @@ template <typename C> __device__ __forceinline__ C buf_load_c(__amdgpu_buffer_rs
   else
     return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
 }
+// real part of complex element idx of a double2 or float2 buffer
+template <typename C>
+__device__ __forceinline__ auto buf_load_re(__amdgpu_buffer_rsrc_t r, int idx) {
+  if constexpr (sizeof(C) == 16)
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 16, 0, 0));
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 8, 0, 0));
+}
 template <typename C>
 __device__ __forceinline__ void buf_store_c(__amdgpu_buffer_rsrc_t r, int idx, C x) {
   if constexpr (sizeof(C) == 16) {

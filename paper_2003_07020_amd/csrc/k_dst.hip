@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256, WAVES) k_dst3_scale(const C* zin, C* zout
     const int j = n1 < E::N1 / 2 ? idx - 1 : P - idx - 1;
     const R sg = n1 < E::N1 / 2 ? (R)1 : (R)-1;
     C x;
-    if (DUAL && dual[b]) x = cmk<C>(buf_load_c<C>(rs[b], j).x, buf_load_c<C>(rs2[b], j).x);
+    if (DUAL && dual[b]) x = cmk<C>(buf_load_re<C>(rs[b], j), buf_load_re<C>(rs2[b], j));
     else x = buf_load_c<C>(rs[b], j);
     return cmk<C>(sg * x.x, sg * x.y);
   };

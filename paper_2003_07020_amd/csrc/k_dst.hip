@@ -273,6 +273,8 @@ static int dst_cols(const Plan& p, C* z, const C* tw) {
 
 #define RFDE_P_SWITCH(Pval, FN, ...)           \
   switch (Pval) {                              \
+    case 4: return FN<4, __VA_ARGS__;          \
+    case 8: return FN<8, __VA_ARGS__;          \
     case 16: return FN<16, __VA_ARGS__;        \
     case 32: return FN<32, __VA_ARGS__;        \
     case 64: return FN<64, __VA_ARGS__;        \

@@ -7,7 +7,7 @@
 namespace rfde {
 
 constexpr int RED_BLOCKS = 1024;  // partials per reduced quantity
-constexpr int VCHUNK = 4;         // vectors handled per pass of the multi-dot kernel
+constexpr int VCHUNK = 4;         // vectors handled per pass of k_dot_partial
 
 __device__ __forceinline__ double block_sum_256(double v, double* sh) {
   const int t = threadIdx.x;
@@ -53,78 +53,52 @@ __global__ void __launch_bounds__(256) k_dot_final(const double* __restrict__ pa
   if (threadIdx.x == 0) out[v] = do_sqrt ? sqrt(s) : s;
 }
 
-int launch_multi_dot(const Plan& p, const double* V, int nvec, const double* w, double* out) {
-  const size_t n = p.N();
-  for (int v0 = 0; v0 < nvec; v0 += VCHUNK) {
-    const int nv = std::min(VCHUNK, nvec - v0);
-    k_dot_partial<<<RED_BLOCKS, 256, 0, p.stream>>>(V + (size_t)v0 * n, n, nv, w, n,
-                                                     p.red + (size_t)v0 * RED_BLOCKS);
-    RFDE_HIP(hipGetLastError());
-  }
-  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out, 0);
-  RFDE_HIP(hipGetLastError());
-  return RFDE_OK;
-}
-
-// ---- CGS2 in three sweeps over the basis (classical Gram-Schmidt applied twice) ----
-// Sweep A: h1 = V^T w.  Sweep B: w1 = w - V h1, and h2 = V^T w1 accumulated in the same sweep
-// (each element of w1 is formed in registers, then multiplied by the basis values just read).
-// Sweep C: w2 = w1 - V h2 and |w2|^2.  The arithmetic is that of CGS2; one sweep over V and w is
-// saved, and the host reads h1, h2 and |w2| once per Arnoldi step.
+// ---- CGS2 in two sweeps over the stored basis U (the scheme is described in krylov.hpp) ----
 constexpr int CGS_ACC = 16;  // dot products accumulated per sweep
-enum { CGS_DOT = 0, CGS_AXPY_DOT = 1, CGS_AXPY_NRM = 2 };
+enum { CGS_DOT = 0, CGS_AXPY_DOT = 1 };
 
-// MODE CGS_DOT:      partial[v][b] = sum_i V[v][i] w[i], v < nv.
-// MODE CGS_AXPY_DOT: w[i] -= sum_{v < nall} h[v] V[v][i]; partial[v][b] = sum_i V[v][i] w[i]
-//                    (the updated w), v < nv.
-// MODE CGS_AXPY_NRM: w[i] -= sum_{v < nall} h[v] V[v][i]; partial[0][b] = sum_i w[i]^2.
-// V holds the vectors at stride n.  NV > 0: nv = NV and, for the correcting modes, nall = NV,
+// MODE CGS_DOT:      partial[v][b] = sum_i U[v][i] w[i], v < nv.
+// MODE CGS_AXPY_DOT: w[i] -= sum_{v < nall} c[v] U[v][i]; partial[v][b] = sum_i U[v][i] w[i]
+//                    (the updated w), v < nv; pnrm[b] = sum_i w[i]^2 (the updated w).
+// U holds the vectors at stride n.  NV > 0: nv = NV and, for the correcting mode, nall = NV,
 // known at compile time so every basis value of an element is loaded before any is used (all
 // loads in flight together); NV = 0: any nall (> CGS_ACC) with nv = CGS_ACC, by loops.
 // Elements are read in pairs (16-byte loads) with the last element of an odd n done alone.
 template <int MODE, int NV>
 __global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const double* __restrict__ V,
-                                             size_t n, int nall, const double* __restrict__ h,
-                                             double* __restrict__ partial) {
-  constexpr int NACC = MODE == CGS_AXPY_NRM ? 1 : (NV > 0 ? NV : CGS_ACC);
-  double acc[NACC];
+                                             size_t n, int nall, const double* __restrict__ c,
+                                             double* __restrict__ partial,
+                                             double* __restrict__ pnrm) {
+  constexpr int NACC = NV > 0 ? NV : CGS_ACC;
+  constexpr int NOUT = MODE == CGS_AXPY_DOT ? NACC + 1 : NACC;  // the last: |w|^2
+  double acc[NOUT];
 #pragma unroll
-  for (int v = 0; v < NACC; ++v) acc[v] = 0.0;
+  for (int v = 0; v < NOUT; ++v) acc[v] = 0.0;
   auto element = [&](size_t i, double wi) -> double {
+    double vv[NACC];
     if constexpr (NV > 0) {
-      double vv[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) vv[v] = V[(size_t)v * n + i];
       if constexpr (MODE != CGS_DOT) {
         double s = 0.0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s = fma(h[v], vv[v], s);
+        for (int v = 0; v < NV; ++v) s = fma(c[v], vv[v], s);
         wi -= s;
-      }
-      if constexpr (MODE == CGS_AXPY_NRM) {
-        acc[0] = fma(wi, wi, acc[0]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = fma(vv[v], wi, acc[v]);
       }
     } else {
       static_assert(MODE != CGS_DOT, "dot sweeps take at most CGS_ACC vectors per launch");
-      double vv[CGS_ACC];
       double s = 0.0;
 #pragma unroll
       for (int v = 0; v < CGS_ACC; ++v) {
         vv[v] = V[(size_t)v * n + i];
-        s = fma(h[v], vv[v], s);
+        s = fma(c[v], vv[v], s);
       }
-      for (int v = CGS_ACC; v < nall; ++v) s = fma(h[v], V[(size_t)v * n + i], s);
+      for (int v = CGS_ACC; v < nall; ++v) s = fma(c[v], V[(size_t)v * n + i], s);
       wi -= s;
-      if constexpr (MODE == CGS_AXPY_NRM) {
-        acc[0] = fma(wi, wi, acc[0]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < CGS_ACC; ++v) acc[v] = fma(vv[v], wi, acc[v]);
-      }
     }
+#pragma unroll
+    for (int v = 0; v < NACC; ++v) acc[v] = fma(vv[v], wi, acc[v]);
+    if constexpr (MODE == CGS_AXPY_DOT) acc[NACC] = fma(wi, wi, acc[NACC]);
     return wi;
   };
   const size_t n2 = n / 2;
@@ -139,33 +113,35 @@ __global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const doubl
   }
   // per-wave sums of every accumulator, then one barrier and the four wave sums per value in
   // the fixed order (w0 + w1) + (w2 + w3)
-  __shared__ double shv[4][NACC];
+  __shared__ double shv[4][NOUT];
 #pragma unroll
-  for (int v = 0; v < NACC; ++v) {
+  for (int v = 0; v < NOUT; ++v) {
     double r = acc[v];
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) r += __shfl_xor(r, m);
     if ((threadIdx.x & 63) == 0) shv[threadIdx.x >> 6][v] = r;
   }
   __syncthreads();
-  if ((int)threadIdx.x < NACC) {
+  if ((int)threadIdx.x < NOUT) {
     const int v = threadIdx.x;
-    partial[v * RED_BLOCKS + blockIdx.x] = (shv[0][v] + shv[1][v]) + (shv[2][v] + shv[3][v]);
+    const double t = (shv[0][v] + shv[1][v]) + (shv[2][v] + shv[3][v]);
+    if (v < NACC) partial[v * RED_BLOCKS + blockIdx.x] = t;
+    else pnrm[blockIdx.x] = t;
   }
 }
 
 // launch of mode MODE over nv (1..CGS_ACC) vectors known at compile time, or NV = 0
 template <int MODE>
 static int cgs_launch(const Plan& p, double* w, const double* V, int nall, int nv,
-                      const double* h, double* partial) {
+                      const double* c, double* partial, double* pnrm) {
   const size_t n = p.N();
 #define RFDE_CGS_CASE(K)                                                                     \
   case K:                                                                                    \
-    k_cgs<MODE, K><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nall, h, partial);             \
+    k_cgs<MODE, K><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nall, c, partial, pnrm);       \
     break;
   if (MODE != CGS_DOT && nall > CGS_ACC) {
     if constexpr (MODE != CGS_DOT)
-      k_cgs<MODE, 0><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nall, h, partial);
+      k_cgs<MODE, 0><<<RED_BLOCKS, 256, 0, p.stream>>>(w, V, n, nall, c, partial, pnrm);
   } else {
     switch (nv) {
       RFDE_CGS_CASE(1) RFDE_CGS_CASE(2) RFDE_CGS_CASE(3) RFDE_CGS_CASE(4)
@@ -180,30 +156,135 @@ static int cgs_launch(const Plan& p, double* w, const double* V, int nall, int n
   return RFDE_OK;
 }
 
-int launch_cgs2(const Plan& p, const double* V, int nvec, double* w, double* out) {
+// Sum over the 64 lanes of a wave in a fixed butterfly order (every lane gets the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+// One wave, lane i: x_i of R^T x = y (forward substitution), R of order nvec (<= 64), lane i
+// holding row i of R in rrow[] and y_i in yi.  Lanes at or past nvec return 0.
+__device__ __forceinline__ double tri_lower_t(const double* rrow, double yi, int nvec,
+                                              const double* __restrict__ R) {
+  const int lane = threadIdx.x;
+  double x = 0.0;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    if (k < nvec) {
+      const double sum = wave_sum(lane < k ? rrow[k] * x : 0.0);
+      const double yk = __shfl(yi, k);
+      const double xk = (yk - sum) / R[k + CGS2_R_LD * k];
+      if (lane == k) x = xk;
+    }
+  }
+  return x;
+}
+
+// sweep A's coefficients: h1 = R^{-T} a, c1 = R^{-1} h1 (one wave)
+__global__ void __launch_bounds__(64) k_cgs2_tri_a(const double* __restrict__ ab,
+                                                   const double* __restrict__ R, int nvec,
+                                                   double* __restrict__ h1,
+                                                   double* __restrict__ c1) {
+  const int lane = threadIdx.x;
+  double rrow[64], rcol[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    rrow[k] = R[lane + CGS2_R_LD * k];  // R(lane, k)
+    rcol[k] = R[k + CGS2_R_LD * lane];  // R(k, lane)
+  }
+  const double a = lane < nvec ? ab[lane] : 0.0;
+  const double h = tri_lower_t(rrow, a, nvec, R);
+  // back substitution R c = h: c_k = (h_k - sum_{i > k} R(k, i) c_i) / R(k, k)
+  double x = 0.0;
+#pragma unroll
+  for (int k = 63; k >= 0; --k) {
+    if (k < nvec) {
+      const double sum = wave_sum(lane > k && lane < nvec ? rcol[k] * x : 0.0);
+      const double hk = __shfl(h, k);
+      const double xk = (hk - sum) / R[k + CGS2_R_LD * k];
+      if (lane == k) x = xk;
+    }
+  }
+  if (lane < nvec) {
+    h1[lane] = h;
+    c1[lane] = x;
+  }
+}
+
+// sweep B's coefficients: h2 = R^{-T} b, s = |w1|^2 from the partials, n = sqrt(s - |h2|^2);
+// appends column nvec of R (h2, n), writes the subdiagonal n and vs[nvec] = 1 / sqrt(s).
+__global__ void __launch_bounds__(64) k_cgs2_tri_b(const double* __restrict__ ab,
+                                                   const double* __restrict__ pnrm,
+                                                   double* __restrict__ R, int nvec,
+                                                   double* __restrict__ h2,
+                                                   double* __restrict__ nrm,
+                                                   double* __restrict__ vs) {
+  const int lane = threadIdx.x;
+  double rrow[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) rrow[k] = R[lane + CGS2_R_LD * k];
+  const double b = lane < nvec ? ab[lane] : 0.0;
+  const double h = tri_lower_t(rrow, b, nvec, R);
+  double part = 0.0;
+  for (int t = lane; t < RED_BLOCKS; t += 64) part += pnrm[t];
+  const double s = wave_sum(part);
+  const double hh = wave_sum(lane < nvec ? h * h : 0.0);
+  const double n2 = s - hh;
+  const double nv = n2 > 0.0 ? sqrt(n2) : 0.0;
+  if (lane < nvec) {
+    h2[lane] = h;
+    R[lane + CGS2_R_LD * nvec] = h;
+  }
+  if (lane == 0) {
+    R[nvec + CGS2_R_LD * nvec] = nv;
+    *nrm = nv;
+    vs[nvec] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_cgs2_start(double* __restrict__ R,
+                                                   double* __restrict__ vs, double beta) {
+  if (threadIdx.x == 0) {
+    R[0] = beta;
+    vs[0] = 1.0 / beta;
+  }
+}
+
+int launch_cgs2_start(const Plan& p, double beta, double* out) {
+  k_cgs2_start<<<1, 64, 0, p.stream>>>(p.red + CGS2_R_OFF, out + CGS2_VS, beta);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+int launch_cgs2(const Plan& p, const double* U, int nvec, double* w, double* out) {
+  if (nvec < 1 || nvec > 64) return RFDE_EINVAL;
   const size_t n = p.N();
-  // sweep A: h1 -> out[0 .. nvec)
+  double* R = p.red + CGS2_R_OFF;
+  double* pn = p.red + (size_t)64 * RED_BLOCKS;  // partials of |w1|^2
+  // sweep A: a = U^T w -> h1, c1
   for (int v0 = 0; v0 < nvec; v0 += CGS_ACC) {
     const int nv = std::min(CGS_ACC, nvec - v0);
-    RFDE_TRY(cgs_launch<CGS_DOT>(p, w, V + (size_t)v0 * n, nv, nv, nullptr,
-                                 p.red + (size_t)v0 * RED_BLOCKS));
+    RFDE_TRY(cgs_launch<CGS_DOT>(p, w, U + (size_t)v0 * n, nv, nv, nullptr,
+                                 p.red + (size_t)v0 * RED_BLOCKS, nullptr));
   }
-  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out, 0);
+  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out + CGS2_AB, 0);
   RFDE_HIP(hipGetLastError());
-  // sweep B: w -= V h1 and the dot products with the first CGS_ACC vectors; the rest (if any)
-  // by dot sweeps; h2 -> out[CGS2_H2 ..)
-  RFDE_TRY(cgs_launch<CGS_AXPY_DOT>(p, w, V, nvec, std::min(CGS_ACC, nvec), out, p.red));
+  k_cgs2_tri_a<<<1, 64, 0, p.stream>>>(out + CGS2_AB, R, nvec, out, out + CGS2_C);
+  RFDE_HIP(hipGetLastError());
+  // sweep B: w1 = w - U c1 with its dot products with the first CGS_ACC vectors and |w1|^2;
+  // the rest (if any) by dot sweeps; then h2, n and the new column of R
+  RFDE_TRY(cgs_launch<CGS_AXPY_DOT>(p, w, U, nvec, std::min(CGS_ACC, nvec), out + CGS2_C, p.red,
+                                    pn));
   for (int v0 = CGS_ACC; v0 < nvec; v0 += CGS_ACC) {
     const int nv = std::min(CGS_ACC, nvec - v0);
-    RFDE_TRY(cgs_launch<CGS_DOT>(p, w, V + (size_t)v0 * n, nv, nv, nullptr,
-                                 p.red + (size_t)v0 * RED_BLOCKS));
+    RFDE_TRY(cgs_launch<CGS_DOT>(p, w, U + (size_t)v0 * n, nv, nv, nullptr,
+                                 p.red + (size_t)v0 * RED_BLOCKS, nullptr));
   }
-  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out + CGS2_H2, 0);
+  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out + CGS2_AB, 0);
   RFDE_HIP(hipGetLastError());
-  // sweep C: w -= V h2 and |w| -> out[CGS2_NRM]
-  RFDE_TRY(cgs_launch<CGS_AXPY_NRM>(p, w, V, nvec, std::min(CGS_ACC, nvec), out + CGS2_H2,
-                                    p.red));
-  k_dot_final<<<1, 256, 0, p.stream>>>(p.red, out + CGS2_NRM, 1);
+  k_cgs2_tri_b<<<1, 64, 0, p.stream>>>(out + CGS2_AB, pn, R, nvec, out + CGS2_H2,
+                                       out + CGS2_NRM, out + CGS2_VS);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
@@ -256,23 +337,6 @@ int launch_multi_axpy(const Plan& p, double* w, const double* V, int nvec, const
     default: k_multi_axpy<0><<<blocks, 256, 0, p.stream>>>(w, V, n, nvec, coef, sign);
   }
 #undef RFDE_AXPY_CASE
-  RFDE_HIP(hipGetLastError());
-  return RFDE_OK;
-}
-
-// y = x * s (inv = 0) or y = x / s (inv = 1), s a device scalar
-__global__ void k_scale_copy(const double* x, double* y, size_t n,
-                             const double* __restrict__ s, int inv) {
-  const double a = inv ? 1.0 / s[0] : s[0];
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    y[i] = x[i] * a;
-}
-
-int launch_scale_copy(const Plan& p, const double* x, double* y, const double* scal_dev, int inv) {
-  const size_t n = p.N();
-  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
-  k_scale_copy<<<blocks, 256, 0, p.stream>>>(x, y, n, scal_dev, inv);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

@@ -18,6 +18,7 @@
 // Lt >= 2 Nt - 1 (forward FFT, product with the precomputed DFT of the kernel, inverse FFT),
 // all in LDS.  Step (c) uses sum_n Z_n theta^{-n j} = conj(sum_n conj(Z_n) theta^{n j}).
 #include "fft_lds.hpp"
+#include "krylov.hpp"
 #include "rfde_internal.hpp"
 
 namespace rfde {
@@ -25,10 +26,12 @@ namespace rfde {
 template <int N, int NB, int NT, typename C, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C* __restrict__ z1,
                                                  const double* __restrict__ s,
+                                                 const double* __restrict__ vs,
                                                  const C* __restrict__ tw, int S,
                                                  const int* __restrict__ live) {
   if (live && *live == 0) return;
   using R = typename cplx_traits<C>::real;
+  const double vsc = vs ? vs[0] : 1.0;
   constexpr int LDN = N + 1;
   __shared__ C buf[NB * LDN];
   constexpr int TS = 2 * NB;
@@ -36,7 +39,7 @@ __global__ void __launch_bounds__(NT) k_time_fwd(const double* __restrict__ v, C
   auto load = [&](int f, int j) -> C {
     const int i = i0 + 2 * f;
     const double* row = v + (size_t)j * S;
-    const double sj = s[j];
+    const double sj = s[j] * vsc;
     const R a = (i < S) ? (R)(sj * row[i]) : (R)0;
     const R b = (i + 1 < S) ? (R)(sj * row[i + 1]) : (R)0;
     return cmk<C>(a, b);
@@ -93,12 +96,14 @@ __global__ void __launch_bounds__(NT) k_time_inv(const C* __restrict__ z2, doubl
 template <int LB, int NB, int NT, typename C, int MAXR = 16>
 __global__ void __launch_bounds__(NT) k_time_fwd_bs(const double* __restrict__ v, C* __restrict__ z1,
                                                     const double* __restrict__ s,
+                                                    const double* __restrict__ vs,
                                                     const C* __restrict__ tw,
                                                     const C* __restrict__ chirp,
                                                     const C* __restrict__ bhat, int S, int Nt,
                                                     const int* __restrict__ live) {
   if (live && *live == 0) return;
   using R = typename cplx_traits<C>::real;
+  const double vsc = vs ? vs[0] : 1.0;
   constexpr int LDN = LB + 1;
   __shared__ C buf[NB * LDN];
   constexpr int TS = 2 * NB;
@@ -107,7 +112,7 @@ __global__ void __launch_bounds__(NT) k_time_fwd_bs(const double* __restrict__ v
     if (j >= Nt) return cmk<C>((R)0, (R)0);
     const int i = i0 + 2 * f;
     const double* row = v + (size_t)j * S;
-    const double sj = s[j];
+    const double sj = s[j] * vsc;
     const R a = (i < S) ? (R)(sj * row[i]) : (R)0;
     const R b = (i + 1 < S) ? (R)(sj * row[i + 1]) : (R)0;
     return cmul(cmk<C>(a, b), chirp[j]);
@@ -243,12 +248,12 @@ constexpr int time_nt() {
 }
 
 template <int N, typename C, int V>
-static int tf_fwd_v(const Plan& p, const double* v, void* z1, const C* tw) {
+static int tf_fwd_v(const Plan& p, const double* v, void* z1, const C* tw, const double* vs) {
   constexpr int NB = time_nb<N, C, V>();
   constexpr int NT = time_nt<N, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_fwd<N, NB, NT, C, time_maxr<N, V>()><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, p.S,
-                                                                         p.live);
+  k_time_fwd<N, NB, NT, C, time_maxr<N, V>()><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, vs, tw,
+                                                                         p.S, p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
@@ -283,12 +288,12 @@ static bool time_narrow(const Plan& p) {
   return NB >= 2 && (p.S + 2 * NB - 1) / (2 * NB) < device_cus(p.device);
 }
 template <int N, typename C>
-static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw) {
+static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw, const double* vs) {
   if (p.tv_time == 1 || (p.tv_time == 0 && time_narrow<N, C>(p)))
-    return tf_fwd_v<N, C, 1>(p, v, z1, tw);
-  if (p.tv_time == 2) return tf_fwd_v<N, C, 2>(p, v, z1, tw);
-  if (p.tv_time == 3) return tf_fwd_v<N, C, 3>(p, v, z1, tw);
-  return tf_fwd_v<N, C, 0>(p, v, z1, tw);
+    return tf_fwd_v<N, C, 1>(p, v, z1, tw, vs);
+  if (p.tv_time == 2) return tf_fwd_v<N, C, 2>(p, v, z1, tw, vs);
+  if (p.tv_time == 3) return tf_fwd_v<N, C, 3>(p, v, z1, tw, vs);
+  return tf_fwd_v<N, C, 0>(p, v, z1, tw, vs);
 }
 template <int N, typename C>
 static int tf_inv(const Plan& p, const void* z2, double* v, const C* tw) {
@@ -301,12 +306,12 @@ static int tf_inv(const Plan& p, const void* z2, double* v, const C* tw) {
 
 template <int LB, typename C, int V>
 static int tf_fwd_bs_v(const Plan& p, const double* v, void* z1, const C* tw, const C* w,
-                       const C* bh) {
+                       const C* bh, const double* vs) {
   constexpr int NB = time_nb<LB, C, V>();
   constexpr int NT = time_nt<LB, C, V>();
   const int blocks = (p.S + 2 * NB - 1) / (2 * NB);
-  k_time_fwd_bs<LB, NB, NT, C, time_maxr<LB, V>()><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, tw, w, bh, p.S, p.Nt,
-                                                            p.live);
+  k_time_fwd_bs<LB, NB, NT, C, time_maxr<LB, V>()><<<blocks, NT, 0, p.stream>>>(v, (C*)z1, p.s, vs, tw, w, bh, p.S,
+                                                            p.Nt, p.live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
@@ -323,11 +328,11 @@ static int tf_inv_bs_v(const Plan& p, const void* z2, double* v, const C* tw, co
 }
 template <int LB, typename C>
 static int tf_fwd_bs(const Plan& p, const double* v, void* z1, const C* tw, const C* w,
-                     const C* bh) {
+                     const C* bh, const double* vs) {
   // (variant 3 has no Bluestein instantiation: it runs the default shape)
-  if (p.tv_time == 1) return tf_fwd_bs_v<LB, C, 1>(p, v, z1, tw, w, bh);
-  if (p.tv_time == 2) return tf_fwd_bs_v<LB, C, 2>(p, v, z1, tw, w, bh);
-  return tf_fwd_bs_v<LB, C, 0>(p, v, z1, tw, w, bh);
+  if (p.tv_time == 1) return tf_fwd_bs_v<LB, C, 1>(p, v, z1, tw, w, bh, vs);
+  if (p.tv_time == 2) return tf_fwd_bs_v<LB, C, 2>(p, v, z1, tw, w, bh, vs);
+  return tf_fwd_bs_v<LB, C, 0>(p, v, z1, tw, w, bh, vs);
 }
 template <int LB, typename C>
 static int tf_inv_bs(const Plan& p, const void* z2, double* v, const C* tw, const C* w,
@@ -384,15 +389,19 @@ int launch_bluestein_setup(const Plan& p) {
     default: return RFDE_EINVAL;                   \
   }
 
-int launch_time_fwd(const Plan& p, const double* v, void* z1) {
+int launch_time_fwd_scaled(const Plan& p, const double* v, void* z1, const double* vs) {
   if (p.Lt != p.Nt) {
     if (p.opts.precond_bits == 32) {
-      RFDE_LB_SWITCH(tf_fwd_bs, float2, p, v, z1, p.twNt32, p.chirp32, p.bhat32);
+      RFDE_LB_SWITCH(tf_fwd_bs, float2, p, v, z1, p.twNt32, p.chirp32, p.bhat32, vs);
     }
-    RFDE_LB_SWITCH(tf_fwd_bs, double2, p, v, z1, p.twNt, p.chirp, p.bhat);
+    RFDE_LB_SWITCH(tf_fwd_bs, double2, p, v, z1, p.twNt, p.chirp, p.bhat, vs);
   }
-  if (p.opts.precond_bits == 32) { RFDE_NT_SWITCH(tf_fwd, float2, p, v, z1, p.twNt32); }
-  RFDE_NT_SWITCH(tf_fwd, double2, p, v, z1, p.twNt);
+  if (p.opts.precond_bits == 32) { RFDE_NT_SWITCH(tf_fwd, float2, p, v, z1, p.twNt32, vs); }
+  RFDE_NT_SWITCH(tf_fwd, double2, p, v, z1, p.twNt, vs);
+}
+
+int launch_time_fwd(const Plan& p, const double* v, void* z1) {
+  return launch_time_fwd_scaled(p, v, z1, nullptr);
 }
 
 int launch_time_inv(const Plan& p, const void* z2, double* v) {

@@ -113,8 +113,8 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
   RFDE_TRY(dalloc(p, &p->wvec, N, &ws));
   RFDE_TRY(dalloc(p, &p->xvec, N, &ws));
   RFDE_TRY(dalloc(p, &p->Fvec, N, &ws));
-  RFDE_TRY(dalloc(p, &p->red, (size_t)70 * 1024, &ws));
-  RFDE_TRY(dalloc(p, &p->redout, 256, &ws));
+  RFDE_TRY(dalloc(p, &p->red, CGS2_RED_SIZE, &ws));
+  RFDE_TRY(dalloc(p, &p->redout, CGS2_OUT_SIZE, &ws));
   RFDE_HIP(hipHostMalloc((void**)&p->hred, 256 * sizeof(double), hipHostMallocDefault));
   for (auto& e : p->ev) RFDE_HIP(hipEventCreate(&e));
   p->workspace_bytes = ws;
@@ -195,12 +195,15 @@ static int pinv_step_b(const Plan& p, const void* z1, void* z2) {
   return launch_tau_solve(p, z1, z2);
 }
 
-int apply_pinv(Plan& p, const double* v, double* z) {
-  RFDE_TRY(launch_time_fwd(p, v, p.zf));
+// z = P^-1 (v * vs[0]) (vs == nullptr: P^-1 v)
+static int apply_pinv_scaled(Plan& p, const double* v, double* z, const double* vs) {
+  RFDE_TRY(launch_time_fwd_scaled(p, v, p.zf, vs));
   RFDE_TRY(pinv_step_b(p, p.zf, p.zf));
   RFDE_TRY(launch_time_inv(p, p.zf, z));
   return RFDE_OK;
 }
+
+int apply_pinv(Plan& p, const double* v, double* z) { return apply_pinv_scaled(p, v, z, nullptr); }
 
 int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M, int Nt,
                  double T, rfde_opts o, hipStream_t stream) {
@@ -505,8 +508,8 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
   double rel = beta / bnorm;
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gvec(m + 1), y(m);
   while (rel > tol && total < p.opts.maxit) {
-    // V_0 = r / beta (in place)
-    RFDE_TRY(launch_scale_copy(p, r, p.vbuf, p.redout, 1));
+    // u_0 = r (already in the first basis slot), |u_0| = beta
+    RFDE_TRY(launch_cgs2_start(p, beta, p.redout));
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(gvec.begin(), gvec.end(), 0.0);
     gvec[0] = beta;
@@ -516,11 +519,13 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
       double* vj = p.vbuf + (size_t)j * N;
       double* zj = p.zbuf + (size_t)j * N;
       double* vn = p.vbuf + (size_t)(j + 1) * N;
+      // z_j = P^-1 (u_j / |u_j|), the direction of step j (the flexible variant allows any)
       RFDE_HIP(hipEventRecord(p.ev[0], st));
-      RFDE_TRY(apply_pinv(p, vj, zj));
+      RFDE_TRY(apply_pinv_scaled(p, vj, zj, p.redout + CGS2_VS + j));
       RFDE_HIP(hipEventRecord(p.ev[1], st));
       RFDE_TRY(timed_matvec(zj, vn));
-      // classical Gram-Schmidt, twice (CGS2), in three sweeps; one read-back per step
+      // classical Gram-Schmidt, twice (CGS2), in two sweeps over the stored vectors; one
+      // read-back per step
       RFDE_TRY(launch_cgs2(p, p.vbuf, j + 1, vn, p.redout));
       RFDE_TRY(fetch(CGS2_NRM + 1));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hr[i] + hr[CGS2_H2 + i];
@@ -533,8 +538,7 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
       }
       if (!std::isfinite(hn)) return RFDE_ENAN;
       H[(size_t)(j + 1) * m + j] = hn;
-      if (hn > 0.0) RFDE_TRY(launch_scale_copy(p, vn, vn, p.redout + CGS2_NRM, 1));
-      else breakdown = true;
+      if (!(hn > 0.0)) breakdown = true;
       // apply previous rotations, then a new one
       for (int i = 0; i < j; ++i) {
         const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];

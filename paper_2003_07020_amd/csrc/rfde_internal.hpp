@@ -187,11 +187,9 @@ int launch_tau_solve(const Plan& p, const void* zin, void* zout);
 int launch_export_factor(const Plan& p, int index, void* dst);
 
 // BLAS-1 (deterministic fixed-order reductions)
-int launch_multi_dot(const Plan& p, const double* V, int nvec, const double* w, double* out);
 int launch_multi_axpy(const Plan& p, double* w, const double* V, int nvec, const double* coef,
                       double sign);
 int launch_nrm2(const Plan& p, const double* x, double* out);
-int launch_scale_copy(const Plan& p, const double* x, double* y, const double* scal_dev, int inv);
 int launch_sub(const Plan& p, const double* a, const double* b, double* out);  // out = a - b
 
 // Logical block index so that each XCD (blocks are dealt round-robin to 8 XCDs) walks a

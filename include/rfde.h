@@ -79,8 +79,9 @@ typedef struct {
   double true_rel_res;   /* ||F - A U|| / ||F|| recomputed at exit                             */
   double ms_setup;       /* plan setup time (g_k, symbols, lambda, factorisation)              */
   double ms_solve;       /* rfde_solve wall time (RHS + FGMRES + true residual)                */
-  double ms_pinv;        /* accumulated time inside preconditioner applications (HIP events)   */
-  double ms_matvec;      /* accumulated time inside all-at-once matvecs (HIP events)           */
+  double ms_pinv;        /* time inside preconditioner applications: the first one's time
+                            (HIP events) times the number of applications                      */
+  double ms_matvec;      /* time inside all-at-once matvecs, estimated the same way            */
   int n_hist;            /* entries used in res_hist                                           */
   double res_hist[256];  /* estimated relative residual after each Arnoldi step (res_hist[0]=1)*/
 } rfde_stats;

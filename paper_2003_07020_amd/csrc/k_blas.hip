@@ -163,90 +163,108 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// One wave, lane i: x_i of R^T x = y (forward substitution), R of order nvec (<= 64), lane i
-// holding row i of R in rrow[] and y_i in yi.  Lanes at or past nvec return 0.
-__device__ __forceinline__ double tri_lower_t(const double* rrow, double yi, int nvec,
-                                              const double* __restrict__ R) {
-  const int lane = threadIdx.x;
-  double x = 0.0;
-#pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    if (k < nvec) {
-      const double sum = wave_sum(lane < k ? rrow[k] * x : 0.0);
-      const double yk = __shfl(yi, k);
-      const double xk = (yk - sum) / R[k + CGS2_R_LD * k];
-      if (lane == k) x = xk;
-    }
-  }
-  return x;
+// The factor is kept as its inverse Q = R^{-1} (upper triangular, column-major, leading
+// dimension CGS2_R_LD): the coefficient maps are then products, one lane per entry, each a
+// sum in a fixed order.  Lane i < nvec returns (Q^T y)_i = sum_{k <= i} Q(k, i) y_k.
+__device__ __forceinline__ double qt_times(const double* __restrict__ Q, const double* ys,
+                                           int nvec) {
+  const int i = threadIdx.x;
+  double t = 0.0;
+  if (i < nvec)
+    for (int k = 0; k <= i; ++k) t = fma(Q[k + CGS2_R_LD * i], ys[k], t);
+  return t;
+}
+// Lane i < nvec returns (Q y)_i = sum_{i <= k < nvec} Q(i, k) y_k.
+__device__ __forceinline__ double q_times(const double* __restrict__ Q, const double* ys,
+                                          int nvec) {
+  const int i = threadIdx.x;
+  double t = 0.0;
+  if (i < nvec)
+    for (int k = i; k < nvec; ++k) t = fma(Q[i + CGS2_R_LD * k], ys[k], t);
+  return t;
 }
 
-// sweep A's coefficients: h1 = R^{-T} a, c1 = R^{-1} h1 (one wave)
-__global__ void __launch_bounds__(64) k_cgs2_tri_a(const double* __restrict__ ab,
-                                                   const double* __restrict__ R, int nvec,
-                                                   double* __restrict__ h1,
-                                                   double* __restrict__ c1) {
+// ys[v] = sum of the RED_BLOCKS partials of value v < nvec (256 threads, fixed order: four
+// strided partials per thread, then the wave sums, then (w0 + w1) + (w2 + w3)).
+__device__ __forceinline__ void sum_partials(const double* __restrict__ partial, int nvec,
+                                             double (*sh)[4], double* ys) {
+  const int t = threadIdx.x;
+  for (int v = 0; v < nvec; ++v) {
+    const double* pv = partial + (size_t)v * RED_BLOCKS;
+    double a = (pv[t] + pv[t + 256]) + (pv[t + 512] + pv[t + 768]);
+    a = wave_sum(a);
+    if ((t & 63) == 0) sh[v][t >> 6] = a;
+  }
+  __syncthreads();
+  if (t < 64) ys[t] = t < nvec ? (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]) : 0.0;
+  __syncthreads();
+}
+
+// Sweep A's coefficients: a = U^T w from the sweep's partials, h1 = Q^T a (= V^T w) to the
+// host-visible h1, c1 = Q h1 to the device.
+__global__ void __launch_bounds__(256) k_cgs2_fin_a(const double* __restrict__ partial,
+                                                    const double* __restrict__ Q, int nvec,
+                                                    double* h1, double* __restrict__ c1) {
+  static_assert(RED_BLOCKS == 1024, "sum_partials reads four partials per thread");
+  __shared__ double sh[64][4], ys[64], hs[64];
+  sum_partials(partial, nvec, sh, ys);
   const int lane = threadIdx.x;
-  double rrow[64], rcol[64];
-#pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    rrow[k] = R[lane + CGS2_R_LD * k];  // R(lane, k)
-    rcol[k] = R[k + CGS2_R_LD * lane];  // R(k, lane)
+  double h = 0.0;
+  if (lane < 64) {
+    h = qt_times(Q, ys, nvec);
+    hs[lane] = h;
   }
-  const double a = lane < nvec ? ab[lane] : 0.0;
-  const double h = tri_lower_t(rrow, a, nvec, R);
-  // back substitution R c = h: c_k = (h_k - sum_{i > k} R(k, i) c_i) / R(k, k)
-  double x = 0.0;
-#pragma unroll
-  for (int k = 63; k >= 0; --k) {
-    if (k < nvec) {
-      const double sum = wave_sum(lane > k && lane < nvec ? rcol[k] * x : 0.0);
-      const double hk = __shfl(h, k);
-      const double xk = (hk - sum) / R[k + CGS2_R_LD * k];
-      if (lane == k) x = xk;
-    }
-  }
+  __syncthreads();
   if (lane < nvec) {
     h1[lane] = h;
-    c1[lane] = x;
+    c1[lane] = q_times(Q, hs, nvec);
   }
 }
 
-// sweep B's coefficients: h2 = R^{-T} b, s = |w1|^2 from the partials, n = sqrt(s - |h2|^2);
-// appends column nvec of R (h2, n), writes the subdiagonal n and vs[nvec] = 1 / sqrt(s).
-__global__ void __launch_bounds__(64) k_cgs2_tri_b(const double* __restrict__ ab,
-                                                   const double* __restrict__ pnrm,
-                                                   double* __restrict__ R, int nvec,
-                                                   double* __restrict__ h2,
-                                                   double* __restrict__ nrm,
-                                                   double* __restrict__ vs) {
+// Sweep B's coefficients: b = U^T w1 and s = |w1|^2 from the partials, h2 = Q^T b, n =
+// sqrt(s - |h2|^2); h2 and n to the host-visible h2 / nrm; appends column nvec of R^{-1},
+// (-Q h2 / n, 1 / n), and vs[nvec] = 1 / sqrt(s).  n = 0 (breakdown: the cycle ends at this
+// step) leaves the column 0.
+__global__ void __launch_bounds__(256) k_cgs2_fin_b(const double* __restrict__ partial,
+                                                    const double* __restrict__ pnrm,
+                                                    double* __restrict__ Q, int nvec, double* h2,
+                                                    double* nrm, double* __restrict__ vs) {
+  __shared__ double sh[65][4], ys[64], hs[64];
+  sum_partials(partial, nvec, sh, ys);
   const int lane = threadIdx.x;
-  double rrow[64];
-#pragma unroll
-  for (int k = 0; k < 64; ++k) rrow[k] = R[lane + CGS2_R_LD * k];
-  const double b = lane < nvec ? ab[lane] : 0.0;
-  const double h = tri_lower_t(rrow, b, nvec, R);
-  double part = 0.0;
-  for (int t = lane; t < RED_BLOCKS; t += 64) part += pnrm[t];
-  const double s = wave_sum(part);
-  const double hh = wave_sum(lane < nvec ? h * h : 0.0);
-  const double n2 = s - hh;
-  const double nv = n2 > 0.0 ? sqrt(n2) : 0.0;
-  if (lane < nvec) {
-    h2[lane] = h;
-    R[lane + CGS2_R_LD * nvec] = h;
+  {  // s: the same fixed order, kept in sh[64]
+    double a = (pnrm[lane] + pnrm[lane + 256]) + (pnrm[lane + 512] + pnrm[lane + 768]);
+    a = wave_sum(a);
+    if ((lane & 63) == 0) sh[64][lane >> 6] = a;
   }
-  if (lane == 0) {
-    R[nvec + CGS2_R_LD * nvec] = nv;
-    *nrm = nv;
-    vs[nvec] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  double h = 0.0;
+  if (lane < 64) {
+    h = qt_times(Q, ys, nvec);
+    hs[lane] = h;
+  }
+  __syncthreads();
+  if (lane < 64) {
+    const double s = (sh[64][0] + sh[64][1]) + (sh[64][2] + sh[64][3]);
+    const double hh = wave_sum(lane < nvec ? h * h : 0.0);
+    const double n2 = s - hh;
+    const double nv = n2 > 0.0 ? sqrt(n2) : 0.0;
+    const double qh = q_times(Q, hs, nvec);
+    if (lane < nvec) {
+      h2[lane] = h;
+      Q[lane + CGS2_R_LD * nvec] = nv > 0.0 ? -qh / nv : 0.0;
+    }
+    if (lane == 0) {
+      Q[nvec + CGS2_R_LD * nvec] = nv > 0.0 ? 1.0 / nv : 0.0;
+      *nrm = nv;
+      vs[nvec] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    }
   }
 }
 
-__global__ void __launch_bounds__(64) k_cgs2_start(double* __restrict__ R,
+__global__ void __launch_bounds__(64) k_cgs2_start(double* __restrict__ Q,
                                                    double* __restrict__ vs, double beta) {
   if (threadIdx.x == 0) {
-    R[0] = beta;
+    Q[0] = 1.0 / beta;
     vs[0] = 1.0 / beta;
   }
 }
@@ -257,10 +275,11 @@ int launch_cgs2_start(const Plan& p, double beta, double* out) {
   return RFDE_OK;
 }
 
-int launch_cgs2(const Plan& p, const double* U, int nvec, double* w, double* out) {
+int launch_cgs2(const Plan& p, const double* U, int nvec, double* w, double* out,
+                double* hout) {
   if (nvec < 1 || nvec > 64) return RFDE_EINVAL;
   const size_t n = p.N();
-  double* R = p.red + CGS2_R_OFF;
+  double* Q = p.red + CGS2_R_OFF;                // R^{-1}
   double* pn = p.red + (size_t)64 * RED_BLOCKS;  // partials of |w1|^2
   // sweep A: a = U^T w -> h1, c1
   for (int v0 = 0; v0 < nvec; v0 += CGS_ACC) {
@@ -268,12 +287,10 @@ int launch_cgs2(const Plan& p, const double* U, int nvec, double* w, double* out
     RFDE_TRY(cgs_launch<CGS_DOT>(p, w, U + (size_t)v0 * n, nv, nv, nullptr,
                                  p.red + (size_t)v0 * RED_BLOCKS, nullptr));
   }
-  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out + CGS2_AB, 0);
-  RFDE_HIP(hipGetLastError());
-  k_cgs2_tri_a<<<1, 64, 0, p.stream>>>(out + CGS2_AB, R, nvec, out, out + CGS2_C);
+  k_cgs2_fin_a<<<1, 256, 0, p.stream>>>(p.red, Q, nvec, hout, out + CGS2_C);
   RFDE_HIP(hipGetLastError());
   // sweep B: w1 = w - U c1 with its dot products with the first CGS_ACC vectors and |w1|^2;
-  // the rest (if any) by dot sweeps; then h2, n and the new column of R
+  // the rest (if any) by dot sweeps; then h2, n and the new column of R^{-1}
   RFDE_TRY(cgs_launch<CGS_AXPY_DOT>(p, w, U, nvec, std::min(CGS_ACC, nvec), out + CGS2_C, p.red,
                                     pn));
   for (int v0 = CGS_ACC; v0 < nvec; v0 += CGS_ACC) {
@@ -281,10 +298,8 @@ int launch_cgs2(const Plan& p, const double* U, int nvec, double* w, double* out
     RFDE_TRY(cgs_launch<CGS_DOT>(p, w, U + (size_t)v0 * n, nv, nv, nullptr,
                                  p.red + (size_t)v0 * RED_BLOCKS, nullptr));
   }
-  k_dot_final<<<nvec, 256, 0, p.stream>>>(p.red, out + CGS2_AB, 0);
-  RFDE_HIP(hipGetLastError());
-  k_cgs2_tri_b<<<1, 64, 0, p.stream>>>(out + CGS2_AB, pn, R, nvec, out + CGS2_H2,
-                                       out + CGS2_NRM, out + CGS2_VS);
+  k_cgs2_fin_b<<<1, 256, 0, p.stream>>>(p.red, pn, Q, nvec, hout + CGS2_H2, hout + CGS2_NRM,
+                                        out + CGS2_VS);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

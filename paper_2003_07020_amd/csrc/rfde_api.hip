@@ -115,7 +115,7 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
   RFDE_TRY(dalloc(p, &p->Fvec, N, &ws));
   RFDE_TRY(dalloc(p, &p->red, CGS2_RED_SIZE, &ws));
   RFDE_TRY(dalloc(p, &p->redout, CGS2_OUT_SIZE, &ws));
-  RFDE_HIP(hipHostMalloc((void**)&p->hred, 256 * sizeof(double), hipHostMallocDefault));
+  RFDE_HIP(hipHostMalloc((void**)&p->hred, 256 * sizeof(double), hipHostMallocMapped));
   for (auto& e : p->ev) RFDE_HIP(hipEventCreate(&e));
   p->workspace_bytes = ws;
   if (p->factor_bytes) {
@@ -445,9 +445,15 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
   const size_t N = p.N();
   hipStream_t st = p.stream;
   double* hr = p.hred;
+  double* hr_dev = nullptr;  // the same pinned buffer in the device address space
+  RFDE_HIP(hipHostGetDevicePointer((void**)&hr_dev, hr, 0));
   rfde_stats loc;
   std::memset(&loc, 0, sizeof(loc));
-  float ms_pinv = 0.f, ms_mv = 0.f;
+  // Only the first preconditioner application and the first matvec of a solve are timed (an
+  // event pair in the stream costs a few microseconds of idle GPU per step); the reported
+  // totals are those times multiplied by the number of applications.
+  float t_pinv = -1.f, t_mv = -1.f;
+  int n_pinv = 0, n_mv = 0;
 
   auto fetch = [&](int count) -> int {
     RFDE_HIP(hipMemcpyAsync(hr, p.redout, count * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -455,15 +461,15 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
     return RFDE_OK;
   };
   auto timed_matvec = [&](const double* v, double* y) -> int {
-    RFDE_HIP(hipEventRecord(p.ev[2], st));
+    if (n_mv++ == 0) RFDE_HIP(hipEventRecord(p.ev[2], st));
     RFDE_TRY(launch_matvec(p, v, y));
-    RFDE_HIP(hipEventRecord(p.ev[3], st));
+    if (n_mv == 1) RFDE_HIP(hipEventRecord(p.ev[3], st));
     return RFDE_OK;
   };
-  auto add_mv_time = [&]() -> int {
-    float t;
-    RFDE_HIP(hipEventElapsedTime(&t, p.ev[2], p.ev[3]));
-    ms_mv += t;
+  // after a synchronisation: read the first application's times once
+  auto read_times = [&]() -> int {
+    if (t_mv < 0.f && n_mv > 0) RFDE_HIP(hipEventElapsedTime(&t_mv, p.ev[2], p.ev[3]));
+    if (t_pinv < 0.f && n_pinv > 0) RFDE_HIP(hipEventElapsedTime(&t_pinv, p.ev[0], p.ev[1]));
     return RFDE_OK;
   };
 
@@ -492,7 +498,7 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
   }
   RFDE_TRY(launch_nrm2(p, r, p.redout));
   RFDE_TRY(fetch(1));
-  if (U_init) RFDE_TRY(add_mv_time());
+  RFDE_TRY(read_times());
   double beta = hr[0];
   if (U_init && !(beta < bnorm)) {
     // the guess does not reduce the residual: fall back to the zero start
@@ -520,22 +526,17 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
       double* zj = p.zbuf + (size_t)j * N;
       double* vn = p.vbuf + (size_t)(j + 1) * N;
       // z_j = P^-1 (u_j / |u_j|), the direction of step j (the flexible variant allows any)
-      RFDE_HIP(hipEventRecord(p.ev[0], st));
+      if (n_pinv == 0) RFDE_HIP(hipEventRecord(p.ev[0], st));
       RFDE_TRY(apply_pinv_scaled(p, vj, zj, p.redout + CGS2_VS + j));
-      RFDE_HIP(hipEventRecord(p.ev[1], st));
+      if (n_pinv++ == 0) RFDE_HIP(hipEventRecord(p.ev[1], st));
       RFDE_TRY(timed_matvec(zj, vn));
-      // classical Gram-Schmidt, twice (CGS2), in two sweeps over the stored vectors; one
-      // read-back per step
-      RFDE_TRY(launch_cgs2(p, p.vbuf, j + 1, vn, p.redout));
-      RFDE_TRY(fetch(CGS2_NRM + 1));
+      // classical Gram-Schmidt, twice (CGS2), in two sweeps over the stored vectors; the
+      // kernels leave h1, h2 and n in the mapped host buffer
+      RFDE_TRY(launch_cgs2(p, p.vbuf, j + 1, vn, p.redout, hr_dev));
+      RFDE_HIP(hipStreamSynchronize(st));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hr[i] + hr[CGS2_H2 + i];
       const double hn = hr[CGS2_NRM];
-      {
-        float t;
-        RFDE_HIP(hipEventElapsedTime(&t, p.ev[0], p.ev[1]));
-        ms_pinv += t;
-        RFDE_TRY(add_mv_time());
-      }
+      RFDE_TRY(read_times());
       if (!std::isfinite(hn)) return RFDE_ENAN;
       H[(size_t)(j + 1) * m + j] = hn;
       if (!(hn > 0.0)) breakdown = true;
@@ -572,7 +573,6 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
     RFDE_TRY(launch_sub(p, p.Fvec, p.wvec, r));
     RFDE_TRY(launch_nrm2(p, r, p.redout));
     RFDE_TRY(fetch(1));
-    RFDE_TRY(add_mv_time());
     beta = hr[0];
     if (!std::isfinite(beta)) return RFDE_ENAN;
     rel = beta / bnorm;
@@ -586,9 +586,9 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
   loc.true_rel_res = rel;
   loc.converged = rel <= tol ? 1 : 0;
   loc.ms_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
-  loc.ms_pinv = ms_pinv;
+  loc.ms_pinv = n_pinv > 0 ? (double)t_pinv * n_pinv : 0.0;
   loc.ms_setup = p.ms_setup;
-  loc.ms_matvec = ms_mv;
+  loc.ms_matvec = n_mv > 0 ? (double)t_mv * n_mv : 0.0;
   if (stats) *stats = loc;
   return loc.converged ? RFDE_OK : RFDE_ENOTCONV;
 }

@@ -114,6 +114,34 @@ def test_exact_initial_guess_needs_no_iteration():
     assert st.converged and st.iters == 0
 
 
+@pytest.mark.parametrize("restart", [1, 17, 64])
+def test_arnoldi_cycle_lengths(restart):
+    # FGMRES(1) (a factor of order 1 in every cycle), FGMRES(17) (its last step projects onto
+    # 17 stored vectors, one past the 16 dot products of a sweep) and FGMRES(64): the
+    # solution matches the oracle's BDF2 march, and the residual estimate of the last step
+    # agrees with the true residual, which holds only if A Z = V H with the implicit
+    # orthonormal basis
+    banner(f"arnoldi cycle restart={restart}")
+    if restart == 1:
+        alpha, M, Nt, tol, kw = 1.5, 63, 16, 1e-10, dict(maxit=400)
+    else:
+        alpha, M, Nt, tol, kw = 1.05, 1023, 16, 1e-13, dict(spatial="tau")
+    p = _plan(alpha, 1.0, M, Nt, tol=tol, restart=restart, **kw)
+    h, tau = aa.mesh(0.0, 1.0, M, 1.0, Nt)
+    u0, f, _ = gen1d(21, M, Nt)
+    U, st, _ = p.solve(to_dev(u0), to_dev(f.ravel()))
+    Uref = aa.bdf2_march(u0, f, aa.jacobian_A(alpha, 1.0, h, M), tau)
+    print(f"restart={restart}: iters={st.iters} restarts={st.restarts} "
+          f"est={st.res_hist[-1]:.3e} true={st.true_rel_res:.3e}", flush=True)
+    assert st.converged and st.true_rel_res <= tol
+    assert rel_max(to_host(U).reshape(Nt, M), Uref) < 1e-9
+    assert abs(np.log10(st.res_hist[-1]) - np.log10(st.true_rel_res)) < 0.5
+    if restart == 1:
+        assert st.restarts == st.iters
+    else:
+        assert st.iters >= 17
+
+
 def test_restart_path_converges():
     banner("restart m=2")
     st = _check_solve(1.8, 1.0, 100, 32, restart=2, maxit=200)

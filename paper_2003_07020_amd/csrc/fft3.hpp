@@ -91,7 +91,9 @@ __device__ __forceinline__ void twiddle_pow(C* v, const C* __restrict__ tw, int 
   }
 }
 
-template <int N1_, int N2_, int N3_, int NB_, int NT_>
+// TWS: stride of the twiddle table, tw[m TWS] = exp(-2 pi i m / N) (a table of a multiple of the
+// length serves).
+template <int N1_, int N2_, int N3_, int NB_, int NT_, int TWS = 1>
 struct Fft3 {
   static constexpr int N1 = N1_, N2 = N2_, N3 = N3_, NB = NB_, NT = NT_;
   static constexpr int N = N1 * N2 * N3;
@@ -189,7 +191,7 @@ struct Fft3 {
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) x[n1] = load(b, f, n1 * T1 + t, n1);
       dft_any<N1, -1>(x);
-      twiddle_pow<N1, -1>(x, tw, t);
+      twiddle_pow<N1, -1>(x, tw, TWS * t);
     }
   }
   template <typename C>
@@ -200,7 +202,7 @@ struct Fft3 {
       dec2(threadIdx.x + b * NT, f, k1, n3);
       C* x = v + b * N2;
       dft_any<N2, -1>(x);
-      twiddle_pow<N2, -1>(x, tw, N1 * n3);
+      twiddle_pow<N2, -1>(x, tw, TWS * N1 * n3);
     }
   }
   // Stage 3 forward, pointwise(f, k, value&) on every X[k], stage 3 inverse.
@@ -224,7 +226,7 @@ struct Fft3 {
       int f, k1, n3;
       dec2(threadIdx.x + b * NT, f, k1, n3);
       C* x = v + b * N2;
-      twiddle_pow<N2, +1>(x, tw, N1 * n3);
+      twiddle_pow<N2, +1>(x, tw, TWS * N1 * n3);
       dft_any<N2, +1>(x);
     }
   }
@@ -236,7 +238,7 @@ struct Fft3 {
       const int t = (threadIdx.x + b * NT) % T1;
       const int f = f_of_b1(b);
       C* x = v + b * N1;
-      twiddle_pow<N1, +1>(x, tw, t);
+      twiddle_pow<N1, +1>(x, tw, TWS * t);
       dft_any<N1, +1>(x);
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) store(b, f, n1 * T1 + t, n1, x[n1]);

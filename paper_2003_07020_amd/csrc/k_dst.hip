@@ -160,6 +160,236 @@ __global__ void __launch_bounds__(256, WAVES) k_dst3_scale(const C* zin, C* zout
   E::run(lds, tw, load, pw, store);
 }
 
+// 1D tau solve of whole rows on a transform of half that length (N = n + 1 = P / 2 >= 256).
+// For x_1..x_{N-1} (x_0 = x_N = 0) let c_j = sin(pi j / N) (x_j + x_{N-j}) + (x_j - x_{N-j}) / 2
+// and F_k = sum_j c_j exp(+2 pi i j k / N).  With O_k = (F_k + F_{N-k}) / 2 and
+// E_k = -i (F_k - F_{N-k}) / 2 the sine sums S_m = sum_j x_j sin(pi j m / N) are S_{2k} = E_k
+// and S_{2k+1} = O_0 + ... + O_k - O_0 / 2 (the identity for real sequences, applied to the
+// real and imaginary parts at once since every coefficient is real).  The solve is
+// z2 = (2 / N) S(d S(z1)) with d_m = 1 / (lambda_r + coef sigma_m).  The first transform runs
+// as the forward stages on conj(c), which give conj(F); the second as the inverse stages, which
+// form the +i sums directly from the stage-3 layout.  Between and after the transforms the
+// spectrum sits in LDS (one complex slot of padding per 8 entries, so that a lane's run of 8
+// consecutive entries starts on a different bank group than its neighbour's); the prefix sums
+// take a fixed order: a thread's KT consecutive entries, then a scan over the lanes of the row.
+// DUAL: rows 0 and nrows - 1 (real lambda, real data) share item 0 as real and imaginary parts,
+// each scaled by its own row's d.
+template <int N, typename C, int WAVES, bool DUAL>
+__global__ void __launch_bounds__(256, WAVES) k_dst_half(const C* zin, C* zout, int nrows,
+                                                         const double2* __restrict__ lambda,
+                                                         const double* __restrict__ sigma,
+                                                         double coef, const C* __restrict__ tw) {
+  using S3 = Split3<N>;
+  using E = Fft3<S3::N1, S3::N2, S3::N3, S3::NB, 256, 2>;
+  using R = typename cplx_traits<C>::real;
+  constexpr int n = N - 1, NB = E::NB, T = 256 / NB, KT = N / 2 / T;
+  constexpr int LDN = N + N / 8;
+  constexpr int CPLX = NB * LDN * 2;
+  constexpr int LDSR = E::LDS > CPLX ? E::LDS : CPLX;
+  static_assert(KT >= 1 && KT * T == N / 2, "whole runs of the prefix sums per thread");
+  static_assert(T % 32 == 0 && T <= 256, "lanes per row");
+  __shared__ R lds[LDSR];
+  __shared__ R wsum[2][4];
+  C* buf = reinterpret_cast<C*>(lds);
+  auto at = [](int f, int k) { return f * LDN + k + (k >> 3); };
+  const int nitems = DUAL ? nrows - 1 : nrows;
+  const int item0 = xcd_remap(blockIdx.x, gridDim.x) * E::NB;
+  auto rowr = [&](const C* z, int r) {
+    const bool ok = r >= 0 && r < nrows;
+    return make_rsrc(z + (ok ? (size_t)r * n : 0), ok ? n * (int)sizeof(C) : 0);
+  };
+  __amdgpu_buffer_rsrc_t rs[E::B1], rs2[E::B1];
+  bool dual[E::B1];
+#pragma unroll
+  for (int b = 0; b < E::B1; ++b) {
+    const int it = item0 + E::f_of_b1(b);
+    dual[b] = DUAL && it == 0;
+    rs[b] = rowr(zin, it < nitems ? it : -1);
+    rs2[b] = rowr(zin, dual[b] ? nrows - 1 : -1);
+  }
+  // x_j of the item, j = 0..N (zero outside 1..n through the descriptor's range)
+  auto xval = [&](int b, int j) -> C {
+    if (DUAL && dual[b]) return cmk<C>(buf_load_re<C>(rs[b], j - 1), buf_load_re<C>(rs2[b], j - 1));
+    return buf_load_c<C>(rs[b], j - 1);
+  };
+  auto sinN = [&](int j) -> R { return -tw[j].y; };  // sin(pi j / N) = sin(2 pi j / P)
+  // stage-1 input: conj(c_idx)
+  auto load = [&](int b, int, int idx, int) -> C {
+    const C x = xval(b, idx), y = xval(b, N - idx);
+    const R sj = sinN(idx);
+    const R cx = sj * (x.x + y.x) + (R)0.5 * (x.x - y.x);
+    const R cy = sj * (x.y + y.y) + (R)0.5 * (x.y - y.y);
+    return cmk<C>(cx, -cy);
+  };
+
+  // Exclusive prefix over the lanes of a row (T consecutive threads) of a per-thread (vx, vy).
+  auto lane_scan = [&](R vx, R vy, R& ex, R& ey) {
+    constexpr int SEG = T < 64 ? T : 64;
+    const int lane = threadIdx.x & 63, sl = lane & (SEG - 1);
+    R ix = vx, iy = vy;
+#pragma unroll
+    for (int d = 1; d < SEG; d <<= 1) {
+      const R tx = __shfl_up(ix, d, SEG), ty = __shfl_up(iy, d, SEG);
+      if (sl >= d) {
+        ix += tx;
+        iy += ty;
+      }
+    }
+    R px = __shfl_up(ix, 1, SEG), py = __shfl_up(iy, 1, SEG);
+    if (sl == 0) px = py = (R)0;
+    if constexpr (T > 64) {
+      const int w = threadIdx.x >> 6;
+      if (lane == 63) {
+        wsum[0][w] = ix;
+        wsum[1][w] = iy;
+      }
+      __syncthreads();
+      const int w0 = (threadIdx.x / T) * (T / 64);
+      R ox = (R)0, oy = (R)0;
+      for (int q = w0; q < w; ++q) {
+        ox += wsum[0][q];
+        oy += wsum[1][q];
+      }
+      px = ox + px;
+      py = oy + py;
+    }
+    ex = px;
+    ey = py;
+  };
+  // Sine sums S_m of row f from F in buf; emit(f, m, S_m) for the thread's m = 2k, 2k + 1,
+  // k = tl KT .. tl KT + KT - 1 (m = 0 is emitted as zero), after a barrier (emit may write buf).
+  const int fs = threadIdx.x / T, tl = threadIdx.x % T;
+  auto sine_sums = [&](auto emit) {
+    const C F0 = buf[at(fs, 0)];
+    C O[KT], Ev[KT];
+    R tx = (R)0, ty = (R)0;
+#pragma unroll
+    for (int i = 0; i < KT; ++i) {
+      const int k = tl * KT + i;
+      const C Fk = buf[at(fs, k)], Fm = buf[at(fs, (N - k) & (N - 1))];
+      O[i] = cmk<C>((R)0.5 * (Fk.x + Fm.x), (R)0.5 * (Fk.y + Fm.y));
+      Ev[i] = cmk<C>((R)0.5 * (Fk.y - Fm.y), (R)-0.5 * (Fk.x - Fm.x));
+      tx += O[i].x;
+      ty += O[i].y;
+    }
+    R sx, sy;
+    lane_scan(tx, ty, sx, sy);
+    sx -= (R)0.5 * F0.x;
+    sy -= (R)0.5 * F0.y;
+    C Sodd[KT];
+#pragma unroll
+    for (int i = 0; i < KT; ++i) {
+      sx += O[i].x;
+      sy += O[i].y;
+      Sodd[i] = cmk<C>(sx, sy);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KT; ++i) {
+      const int k = tl * KT + i;
+      emit(fs, 2 * k, k == 0 ? cmk<C>((R)0, (R)0) : Ev[i]);
+      emit(fs, 2 * k + 1, Sodd[i]);
+    }
+  };
+  // d_m (times 2 / N) of row r as a complex number
+  const double sc = 2.0 / N;
+  auto scale = [&](int r, int m) -> double2 {
+    const double2 lm = lambda[r];
+    const double dr = lm.x + coef * sigma[m - 1], di = lm.y;
+    const double q = dr * dr + di * di;
+    const double s = sc / q;
+    return make_double2(dr * s, -di * s);
+  };
+
+  C v[E::P];
+  // first transform: forward stages on conj(c); F = conj of the result, to LDS
+  E::fwd1(v, tw, load);
+  {
+    auto s1a = [](int i) { return E::a_of_s1(i); };
+    auto s2a = [](int i) { return E::a_of_s2(i); };
+    auto s2b = [](int i) { return E::b_of_s2(i); };
+    auto s3b = [](int i) { return E::b_of_s3(i); };
+    E::template exchange<C>(lds, v, s1a, s2a);
+    E::fwd2(v, tw);
+    E::template exchange<C>(lds, v, s2b, s3b);
+  }
+#pragma unroll
+  for (int b = 0; b < E::B3; ++b) {
+    int f, k1, k2;
+    E::dec3(threadIdx.x + b * 256, f, k1, k2);
+    C* x = v + b * E::N3;
+    dft_any<E::N3, -1>(x);
+#pragma unroll
+    for (int k3 = 0; k3 < E::N3; ++k3)
+      buf[at(f, k1 + E::N1 * k2 + E::N1 * E::N2 * k3)] = cconj(x[k3]);
+  }
+  __syncthreads();
+  // W = d S(z1) (times 2 / N), in place
+  {
+    const int it = min(item0 + fs, nitems - 1);
+    auto emit_w = [&](int f, int m, C Sm) {
+      C w = cmk<C>((R)0, (R)0);
+      if (m >= 1) {
+        if (DUAL && it == 0) {
+          const double da = scale(0, m).x, db = scale(nrows - 1, m).x;
+          w = cmk<C>((R)(Sm.x * da), (R)(Sm.y * db));
+        } else {
+          const double2 d = scale(it, m);
+          w = cmk<C>((R)(Sm.x * d.x - Sm.y * d.y), (R)(Sm.x * d.y + Sm.y * d.x));
+        }
+      }
+      buf[at(f, m)] = w;
+    };
+    sine_sums(emit_w);
+  }
+  __syncthreads();
+  // second transform: c'_k of W into the stage-3 layout, then the inverse stages
+#pragma unroll
+  for (int b = 0; b < E::B3; ++b) {
+    int f, k1, k2;
+    E::dec3(threadIdx.x + b * 256, f, k1, k2);
+    C* x = v + b * E::N3;
+#pragma unroll
+    for (int k3 = 0; k3 < E::N3; ++k3) {
+      const int k = k1 + E::N1 * k2 + E::N1 * E::N2 * k3;
+      const C a = buf[at(f, k)];
+      const C c = k == 0 ? cmk<C>((R)0, (R)0) : buf[at(f, N - k)];
+      const R sk = sinN(k);
+      x[k3] = cmk<C>(sk * (a.x + c.x) + (R)0.5 * (a.x - c.x), sk * (a.y + c.y) + (R)0.5 * (a.y - c.y));
+    }
+    dft_any<E::N3, +1>(x);
+  }
+  __syncthreads();
+  {
+    auto s1a = [](int i) { return E::a_of_s1(i); };
+    auto s2a = [](int i) { return E::a_of_s2(i); };
+    auto s2b = [](int i) { return E::b_of_s2(i); };
+    auto s3b = [](int i) { return E::b_of_s3(i); };
+    E::template exchange<C>(lds, v, s3b, s2b);
+    E::inv2(v, tw);
+    E::template exchange<C>(lds, v, s2a, s1a);
+  }
+  auto store_f = [&](int, int f, int idx, int, C c) { buf[at(f, idx)] = c; };
+  E::inv1(v, tw, store_f);
+  __syncthreads();
+  // z2 = S(W): to LDS, then written out row by row
+  auto emit_out = [&](int f, int m, C Sm) { buf[at(f, m)] = Sm; };
+  sine_sums(emit_out);
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * n; e += 256) {
+    const int f = e / n, m = e - f * n + 1;
+    const int it = item0 + f;
+    if (it >= nitems) continue;
+    const C val = buf[at(f, m)];
+    if (DUAL && it == 0) {
+      zout[m - 1] = cmk<C>(val.x, (R)0);
+      zout[(size_t)(nrows - 1) * n + m - 1] = cmk<C>(val.y, (R)0);
+    } else {
+      zout[(size_t)it * n + m - 1] = val;
+    }
+  }
+}
+
 // Columns of [nf][My][Mx] planes: one block per (frequency, tile of NB columns), columns taken
 // fastest by the threads.  DST along y, divide by lambda_n + coef_x sigma^x_ix +
 // coef_y sigma^y_iy (the x-direction DST has already been applied to the rows), DST again.
@@ -291,8 +521,33 @@ static int dst_cols(const Plan& p, C* z, const C* tw) {
 // Twiddle tables for the DST lengths live after the L tables: they are built on demand by the
 // plan (p.twD holds 2 (Mx+1) entries then 2 (My+1) in 2D; 2 (M+1) in 1D), double and float.
 template <int P, typename C>
+static int dst_half(const Plan& p, const C* zin, C* z, const C* tw) {
+  constexpr int N = P / 2;
+  using E = Fft3<Split3<N>::N1, Split3<N>::N2, Split3<N>::N3, Split3<N>::NB, 256, 2>;
+  // two workgroups per CU: the padded spectrum takes 73.7 KB of LDS
+  constexpr int W = 2;
+  const int nrows = p.nf;
+  const bool dual = p.Nt % 2 == 0 && nrows == p.Nt / 2 + 1 && nrows >= 2;
+  const int items = dual ? nrows - 1 : nrows;
+  const int grid = (items + E::NB - 1) / E::NB;
+  if (dual)
+    k_dst_half<N, C, W, true><<<grid, 256, 0, p.stream>>>(zin, z, nrows, p.lambda, p.sigma,
+                                                         p.coef, tw);
+  else
+    k_dst_half<N, C, W, false><<<grid, 256, 0, p.stream>>>(zin, z, nrows, p.lambda, p.sigma,
+                                                          p.coef, tw);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+// FP64 rows of P >= 512 take the half-length transform.  In FP32 its prefix sums over N / 2
+// entries lose more than the full-length transform does (5.6e-5 relative at M = 4095,
+// alpha = 1.8, where the full length stays within 2e-5), so FP32 keeps the full length.
+template <int P, typename C>
 static int dst_1d(const Plan& p, const C* zin, C* z, const C* tw) {
-  if constexpr (P >= 256) {
+  if constexpr (P >= 512 && sizeof(C) == 16) {
+    return dst_half<P, C>(p, zin, z, tw);
+  } else if constexpr (P >= 256) {
     return dst3_scale<P, C>(p, zin, z, p.nf, p.sigma, p.coef, tw);
   } else {
     if (zin != z)

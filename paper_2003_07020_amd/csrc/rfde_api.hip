@@ -195,15 +195,20 @@ static int pinv_step_b(const Plan& p, const void* z1, void* z2) {
   return launch_tau_solve(p, z1, z2);
 }
 
-// z = P^-1 (v * vs[0]) (vs == nullptr: P^-1 v)
-static int apply_pinv_scaled(Plan& p, const double* v, double* z, const double* vs) {
-  RFDE_TRY(launch_time_fwd_scaled(p, v, p.zf, vs));
+// z = P^-1 (v * vs[0]) (vs == nullptr: P^-1 v), as step (a) into the plan's frequency buffer
+// (pinv_head) and steps (b), (c) from it (pinv_tail)
+static int pinv_head(Plan& p, const double* v, const double* vs) {
+  return launch_time_fwd_scaled(p, v, p.zf, vs);
+}
+static int pinv_tail(Plan& p, double* z) {
   RFDE_TRY(pinv_step_b(p, p.zf, p.zf));
-  RFDE_TRY(launch_time_inv(p, p.zf, z));
-  return RFDE_OK;
+  return launch_time_inv(p, p.zf, z);
 }
 
-int apply_pinv(Plan& p, const double* v, double* z) { return apply_pinv_scaled(p, v, z, nullptr); }
+int apply_pinv(Plan& p, const double* v, double* z) {
+  RFDE_TRY(pinv_head(p, v, nullptr));
+  return pinv_tail(p, z);
+}
 
 int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M, int Nt,
                  double T, rfde_opts o, hipStream_t stream) {
@@ -447,6 +452,14 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
   double* hr = p.hred;
   double* hr_dev = nullptr;  // the same pinned buffer in the device address space
   RFDE_HIP(hipHostGetDevicePointer((void**)&hr_dev, hr, 0));
+  // marks the end of an Arnoldi step's column in the stream (no timing: a timed event stalls
+  // the queue for a few microseconds)
+  hipEvent_t ev_col = nullptr;
+  RFDE_HIP(hipEventCreateWithFlags(&ev_col, hipEventDisableTiming));
+  struct EventGuard {
+    hipEvent_t e;
+    ~EventGuard() { (void)hipEventDestroy(e); }
+  } ev_guard{ev_col};
   rfde_stats loc;
   std::memset(&loc, 0, sizeof(loc));
   // Only the first preconditioner application and the first matvec of a solve are timed (an
@@ -521,19 +534,27 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
     gvec[0] = beta;
     int k = 0;
     bool breakdown = false;
+    bool head_done = false;  // step (a) of this step's P^-1 already queued
     for (int j = 0; j < m; ++j) {
       double* vj = p.vbuf + (size_t)j * N;
       double* zj = p.zbuf + (size_t)j * N;
       double* vn = p.vbuf + (size_t)(j + 1) * N;
       // z_j = P^-1 (u_j / |u_j|), the direction of step j (the flexible variant allows any)
       if (n_pinv == 0) RFDE_HIP(hipEventRecord(p.ev[0], st));
-      RFDE_TRY(apply_pinv_scaled(p, vj, zj, p.redout + CGS2_VS + j));
+      if (!head_done) RFDE_TRY(pinv_head(p, vj, p.redout + CGS2_VS + j));
+      RFDE_TRY(pinv_tail(p, zj));
       if (n_pinv++ == 0) RFDE_HIP(hipEventRecord(p.ev[1], st));
       RFDE_TRY(timed_matvec(zj, vn));
       // classical Gram-Schmidt, twice (CGS2), in two sweeps over the stored vectors; the
       // kernels leave h1, h2 and n in the mapped host buffer
       RFDE_TRY(launch_cgs2(p, p.vbuf, j + 1, vn, p.redout, hr_dev));
-      RFDE_HIP(hipStreamSynchronize(st));
+      RFDE_HIP(hipEventRecord(ev_col, st));
+      // Step (a) of the next step needs only u_{j+1} and its scale, both on the device: queue
+      // it before waiting for the column, so the GPU works while the host reads it (wasted only
+      // if this step turns out to be the last)
+      head_done = j + 1 < m && total + 1 < p.opts.maxit;
+      if (head_done) RFDE_TRY(pinv_head(p, vn, p.redout + CGS2_VS + j + 1));
+      RFDE_HIP(hipEventSynchronize(ev_col));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hr[i] + hr[CGS2_H2 + i];
       const double hn = hr[CGS2_NRM];
       RFDE_TRY(read_times());

@@ -5,7 +5,8 @@
 //     2D: z2_n = (Qy kron Qx) diag(1 / (lambda_n + coef_x sigma^x_i + coef_y sigma^y_j)) (Qy kron Qx) z1_n.
 // A length-n DST-I is computed by a complex FFT of length P = 2(n+1) of the odd extension
 // (0, x_1..x_n, 0, -x_n..-x_1): FFT_k = -2i sum_j x_j sin(pi j k/(n+1)), hence
-// (Q x)_k = sqrt(2/(n+1)) (i/2) FFT_k.  P must be a power of two.
+// (Q x)_k = sqrt(2/(n+1)) (i/2) FFT_k.  P must be a power of two.  1D rows in FP64 with
+// P >= 512 take a complex FFT of length P / 2 instead (k_dst_half).
 #include <type_traits>
 
 #include "buf_io.hpp"

@@ -115,7 +115,10 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
   RFDE_TRY(dalloc(p, &p->Fvec, N, &ws));
   RFDE_TRY(dalloc(p, &p->red, CGS2_RED_SIZE, &ws));
   RFDE_TRY(dalloc(p, &p->redout, CGS2_OUT_SIZE, &ws));
-  RFDE_HIP(hipHostMalloc((void**)&p->hred, 256 * sizeof(double), hipHostMallocMapped));
+  // written by the Arnoldi kernels and read by the host after an event wait: mapped and
+  // coherent, so the writes go straight to host memory
+  RFDE_HIP(hipHostMalloc((void**)&p->hred, 256 * sizeof(double),
+                         hipHostMallocMapped | hipHostMallocCoherent));
   for (auto& e : p->ev) RFDE_HIP(hipEventCreate(&e));
   p->workspace_bytes = ws;
   if (p->factor_bytes) {

@@ -95,11 +95,34 @@ def test_preconditioner_identity(big):
     assert rel_max(Pz, v) < 1e-8
 
 
-def test_solve_full(big):
+@pytest.fixture(scope="module")
+def march(big):
+    # the oracle's sequential BDF2 march of one seeded problem (about 10 s on the host)
     alpha, p, h, tau, A, eps = big
     u0, f, _ = gen1d(2000 + 2, M, NT)
+    return u0, f, aa.bdf2_march(u0, f, A, tau)
+
+
+def test_solve_full(big, march):
+    alpha, p, h, tau, A, eps = big
+    u0, f, Uref = march
     U, st, _ = p.solve(to_dev(u0), to_dev(f.ravel()), tol=1e-10)
     U = to_host(U).reshape(NT, M)
     assert st.converged and st.true_rel_res <= 1e-10
-    Uref = aa.bdf2_march(u0, f, A, tau)
     assert rel_max(U, Uref) < 1e-8
+
+
+def test_solve_full_tau(big, march):
+    # the paper's step (b) (tau/DST-I, the half-length transform at this size) at the
+    # benchmarked shape: the preconditioner differs, the solution of the all-at-once system
+    # does not
+    from paper_2003_07020_amd.rfde import Plan
+    alpha, _, h, tau, A, eps = big
+    u0, f, Uref = march
+    banner(f"large tau solve alpha={alpha}")
+    with Plan.create_1d(alpha, KAPPA, 0.0, 1.0, M, NT, T, tol=1e-10, spatial="tau") as q:
+        U, st, _ = q.solve(to_dev(u0), to_dev(f.ravel()))
+    print(f"tau at M={M}, Nt={NT}: iters={st.iters} true_rel_res={st.true_rel_res:.2e}",
+          flush=True)
+    assert st.converged and st.true_rel_res <= 1e-10
+    assert rel_max(to_host(U).reshape(NT, M), Uref) < 1e-8

@@ -1,6 +1,8 @@
 // Vector kernels of the FGMRES outer iteration (FP64).  Reductions are deterministic: a fixed
 // grid writes one partial per block in a fixed order, and a single block sums the partials
 // with a fixed tree, so repeated runs are bitwise identical.
+#include <cstdint>
+
 #include "krylov.hpp"
 #include "rfde_internal.hpp"
 
@@ -63,7 +65,7 @@ enum { CGS_DOT = 0, CGS_AXPY_DOT = 1 };
 // U holds the vectors at stride n.  NV > 0: nv = NV and, for the correcting mode, nall = NV,
 // known at compile time so every basis value of an element is loaded before any is used (all
 // loads in flight together); NV = 0: any nall (> CGS_ACC) with nv = CGS_ACC, by loops.
-// Elements are read in pairs (16-byte loads) with the last element of an odd n done alone.
+// Elements are read in pairs (16-byte loads) from the first 16-byte boundary of w.
 template <int MODE, int NV>
 __global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const double* __restrict__ V,
                                              size_t n, int nall, const double* __restrict__ c,
@@ -101,15 +103,25 @@ __global__ void __launch_bounds__(256) k_cgs(double* __restrict__ w, const doubl
     if constexpr (MODE == CGS_AXPY_DOT) acc[NACC] = fma(wi, wi, acc[NACC]);
     return wi;
   };
-  const size_t n2 = n / 2;
+  // pairs start where w is 16-byte aligned (w is a basis slot at offset j N: 8-byte aligned
+  // only when N is odd); the element before them and an odd last element are done alone
+  const size_t off = (reinterpret_cast<uintptr_t>(w) & 15) ? 1 : 0;
+  const size_t n2 = (n - off) / 2;
+  double2* wp = reinterpret_cast<double2*>(w + off);
   for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < n2; k += (size_t)RED_BLOCKS * 256) {
-    const double2 wv = reinterpret_cast<const double2*>(w)[k];
-    const double a = element(2 * k, wv.x), b = element(2 * k + 1, wv.y);
-    if constexpr (MODE != CGS_DOT) reinterpret_cast<double2*>(w)[k] = make_double2(a, b);
+    const double2 wv = wp[k];
+    const double a = element(off + 2 * k, wv.x), b = element(off + 2 * k + 1, wv.y);
+    if constexpr (MODE != CGS_DOT) wp[k] = make_double2(a, b);
   }
-  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    const double a = element(n - 1, w[n - 1]);
-    if constexpr (MODE != CGS_DOT) w[n - 1] = a;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (off) {
+      const double a = element(0, w[0]);
+      if constexpr (MODE != CGS_DOT) w[0] = a;
+    }
+    if (off + 2 * n2 < n) {
+      const double a = element(n - 1, w[n - 1]);
+      if constexpr (MODE != CGS_DOT) w[n - 1] = a;
+    }
   }
   // per-wave sums of every accumulator, then one barrier and the four wave sums per value in
   // the fixed order (w0 + w1) + (w2 + w3)

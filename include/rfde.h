@@ -219,7 +219,9 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
   int time_variant;      /* time FFTs: NB >> v transforms per workgroup (v = 0..2), or 3: NB
-                            with 1024 threads and radix-8 passes (power-of-two N_t only)     */
+                            with 1024 threads and radix-8 passes (power-of-two N_t only);
+                            0 takes the half width when the full one leaves CUs idle, and
+                            the shape of 3 for FP64 forward transforms at N_t >= 1024        */
   int matvec_variant;    /* 0 three-stage register FFT (L >= 256); LDS Stockham passes with
                             1 the default workgroup size, 2 the other size, 3 radix 8         */
   int trsv_grid_cap;     /* 0 one workgroup per block; else persistent workgroups             */

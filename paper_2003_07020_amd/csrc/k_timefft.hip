@@ -292,7 +292,10 @@ static int tf_fwd(const Plan& p, const double* v, void* z1, const C* tw, const d
   if (p.tv_time == 1 || (p.tv_time == 0 && time_narrow<N, C>(p)))
     return tf_fwd_v<N, C, 1>(p, v, z1, tw, vs);
   if (p.tv_time == 2) return tf_fwd_v<N, C, 2>(p, v, z1, tw, vs);
-  if (p.tv_time == 3) return tf_fwd_v<N, C, 3>(p, v, z1, tw, vs);
+  // variant 3 by default for the FP64 forward transform at N >= 1024 (M = 4095, N_t = 1024:
+  // 20.2 against 22.5 us; the inverse is faster in the default shape, 20.4 against 21.1 us)
+  constexpr bool fwd3 = N >= 1024 && sizeof(C) == 16;
+  if (p.tv_time == 3 || (p.tv_time == 0 && fwd3)) return tf_fwd_v<N, C, 3>(p, v, z1, tw, vs);
   return tf_fwd_v<N, C, 0>(p, v, z1, tw, vs);
 }
 template <int N, typename C>

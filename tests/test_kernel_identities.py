@@ -1,0 +1,97 @@
+"""Identities the GPU kernels are built on, checked in plain numpy on the CPU (no GPU, no
+oracle): the half-length DST-I of the 1D tau solve and the factored Arnoldi basis of the
+two-sweep CGS2.  The GPU parity tests check the kernels themselves against the oracle."""
+import numpy as np
+import pytest
+
+
+def _sine_sums(x):
+    """S_m = sum_j x_j sin(pi j m / N), m = 1..N-1, by definition (N = len(x) + 1)."""
+    n = len(x)
+    N = n + 1
+    j = np.arange(1, N)
+    return np.sin(np.pi * np.outer(j, j) / N) @ x
+
+
+def _sine_sums_half(x):
+    """The same sums through one complex FFT of length N: c_j = sin(pi j / N)(x_j + x_{N-j}) +
+    (x_j - x_{N-j}) / 2, F_k = sum_j c_j exp(+2 pi i j k / N); S_{2k} = -i (F_k - F_{N-k}) / 2,
+    S_{2k+1} = sum_{q <= k} (F_q + F_{N-q}) / 2 - F_0 / 2."""
+    n = len(x)
+    N = n + 1
+    xx = np.zeros(N + 1, dtype=complex)
+    xx[1:N] = x
+    j = np.arange(N)
+    c = np.sin(np.pi * j / N) * (xx[j] + xx[N - j]) + 0.5 * (xx[j] - xx[N - j])
+    F = np.fft.ifft(c) * N
+    k = np.arange(N // 2)
+    Fm = F[(N - k) % N]
+    O = (F[k] + Fm) / 2
+    E = -1j * (F[k] - Fm) / 2
+    S = np.zeros(N, dtype=complex)
+    S[2 * k[1:]] = E[1:]
+    S[2 * k + 1] = np.cumsum(O) - F[0] / 2
+    return S[1:]
+
+
+@pytest.mark.parametrize("n", [3, 7, 15, 255, 1023])
+def test_half_length_dst(n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    ref = _sine_sums(x)
+    assert np.abs(_sine_sums_half(x) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_factored_cgs2_basis():
+    # two sweeps over the stored vectors U (after the first projection), V = U R^{-1} with the
+    # inverse factor kept: the Hessenberg matrix is classic CGS2's and A Z = V H holds
+    rng = np.random.default_rng(7)
+    n, m = 300, 24
+    A = np.eye(n) + 0.4 * rng.standard_normal((n, n)) / np.sqrt(n)
+    P = np.diag(1.0 + rng.random(n))  # a fixed "preconditioner" direction map
+    r = rng.standard_normal(n)
+    beta = np.linalg.norm(r)
+    # classic CGS2 on a normalised basis
+    V = np.zeros((n, m + 1))
+    V[:, 0] = r / beta
+    H = np.zeros((m + 1, m))
+    for j in range(m):
+        w = A @ (P @ V[:, j])
+        h1 = V[:, : j + 1].T @ w
+        w1 = w - V[:, : j + 1] @ h1
+        h2 = V[:, : j + 1].T @ w1
+        w2 = w1 - V[:, : j + 1] @ h2
+        H[: j + 1, j] = h1 + h2
+        H[j + 1, j] = np.linalg.norm(w2)
+        V[:, j + 1] = w2 / H[j + 1, j]
+    # factored: U, Q = R^{-1}, unit-scaled inputs u_j / |u_j|
+    U = np.zeros((n, m + 1))
+    U[:, 0] = r
+    Q = np.zeros((m + 1, m + 1))
+    Q[0, 0] = 1 / beta
+    vs = np.zeros(m + 1)
+    vs[0] = 1 / beta
+    H2 = np.zeros((m + 1, m))
+    Z = np.zeros((n, m))
+    for j in range(m):
+        k = j + 1
+        Z[:, j] = P @ (U[:, j] * vs[j])
+        w = A @ Z[:, j]
+        h1 = Q[:k, :k].T @ (U[:, :k].T @ w)
+        c1 = Q[:k, :k] @ h1
+        w1 = w - U[:, :k] @ c1
+        s = w1 @ w1
+        h2 = Q[:k, :k].T @ (U[:, :k].T @ w1)
+        nn = np.sqrt(s - h2 @ h2)
+        Q[:k, k] = -(Q[:k, :k] @ h2) / nn
+        Q[k, k] = 1 / nn
+        U[:, k] = w1
+        vs[k] = 1 / np.sqrt(s)
+        H2[:k, j] = h1 + h2
+        H2[k, j] = nn
+    Vimp = U @ Q
+    assert np.abs(Vimp.T @ Vimp - np.eye(m + 1)).max() < 1e-13
+    assert np.abs(A @ Z - Vimp @ H2).max() < 1e-13 * np.abs(A @ Z).max()
+    # the directions differ from classic CGS2's only by the unapplied second projection of
+    # u_j, so the Hessenberg matrices agree to rounding level
+    assert np.abs(H2 - H).max() < 1e-12 * np.abs(H).max()

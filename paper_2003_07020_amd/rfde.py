@@ -54,6 +54,8 @@ def gk(alpha: float, n: int) -> torch.Tensor:
 
 @dataclass
 class SolveStats:
+    """Per-solve statistics (rfde_stats).  ms_pinv / ms_matvec: the first application's time
+    (HIP events) times the number of applications; ms_solve is wall time."""
     iters: int
     restarts: int
     converged: bool

@@ -406,8 +406,21 @@ def measure_2d(args, dev):
         ms_pinv = event_ms(lambda: p.apply_Pinv(v, out=z), 20, s)
         p.apply_A(v, out=z)
         ms_mv = event_ms(lambda: p.apply_A(v, out=z), 20, s)
-        p.destroy()
         nf = Nt // 2 + 1
+        steps = {}
+        if bits == 64:
+            # the time FFTs of steps (a) and (c): 8 B per unknown of v and 16 B per entry of
+            # the half spectrum, read once and written once
+            z1 = p.step_a(v)
+            ms_a = event_ms(lambda: p.step_a(v), 20, s)
+            ms_c = event_ms(lambda: p.step_c(z1), 20, s)
+            step_bytes = 8.0 * N + 16.0 * nf * Mx * My
+            for name, ms in (("step_a", ms_a), ("step_c", ms_c)):
+                rate = step_bytes / (ms * 1e-3) / 1e9
+                steps[name] = {"ms": round(ms, 5), "GB/s": round(rate, 1),
+                               "frac_hbm": round(rate / PEAK_HBM_GBS, 4)}
+            del z1
+        p.destroy()
         csz = 8 if bits == 32 else 16
         # P^-1: step (a) reads v (8 B) and writes the half spectrum; step (b) reads and writes
         # it twice (row DSTs, fused column DST-divide-DST, row DSTs); step (c) reads it, writes v
@@ -420,7 +433,8 @@ def measure_2d(args, dev):
                     "pinv_GB/s": round(pinv_bytes / (ms_pinv * 1e-3) / 1e9, 1),
                     "ms_matvec": round(ms_mv, 4),
                     # read v, write y (16 B per unknown; two passes in practice)
-                    "matvec_GB/s": round(16.0 * N / (ms_mv * 1e-3) / 1e9, 1)}
+                    "matvec_GB/s": round(16.0 * N / (ms_mv * 1e-3) / 1e9, 1),
+                    **({"time_ffts": steps} if steps else {})}
         progress(f"2d form {key} done")
     hx, hy, tau = 1.0 / (Mx + 1), 1.0 / (My + 1), T / Nt
     Tx, Ty = aa.toeplitz_T(gx, Mx), aa.toeplitz_T(gy, My)

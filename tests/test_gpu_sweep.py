@@ -26,8 +26,12 @@ TAU = [(round(float(_rng.uniform(1.05, 2.0)), 3), 2 ** int(k) - 1, int(_rng.inte
 GRID = [(round(float(_rng.uniform(1.1, 1.9)), 3), round(float(_rng.uniform(1.1, 1.9)), 3),
          2 ** int(kx) - 1, 2 ** int(ky) - 1, int(_rng.integers(2, 12)))
         for kx, ky in ((2, 6), (6, 2), (4, 5), (7, 3), (5, 7))]
-# the shortest DST-I lengths (M = 1 and 3: transforms of length 4 and 8)
+# the shortest DST-I lengths (M = 1 and 3: transforms of length 4 and 8); the fewest rows of
+# the half-length kernel (N_t = 2: rows 0 and 1 packed into one item; N_t = 3: two items, none
+# packed) at every rows-per-workgroup count (M = 4095 .. 255), and an odd N_t at M = 4095
 TAU += [(1.5, 1, 4), (1.9, 3, 7)]
+TAU += [(1.7, 4095, 2), (1.3, 4095, 3), (1.6, 2047, 2), (1.4, 1023, 3), (1.8, 511, 2),
+        (1.2, 255, 3), (1.5, 4095, 31)]
 GRID += [(1.3, 1.7, 1, 7, 4), (1.6, 1.2, 3, 3, 5), (1.8, 1.1, 1, 1, 3)]
 
 

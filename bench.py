@@ -195,7 +195,8 @@ def measure_form(bits, args, W, alphas, inputs, dev, spatial="exact"):
             "kernel": "k_ldlt_diag+k_ldlt_panel (factorisation)", "bound": "mfma",
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": None},
-        roofline_step_b={"kernel": "k_trsv" if spatial == "exact" else "k_dst_rows (tau)",
+        roofline_step_b={"kernel": "k_trsv" if spatial == "exact" else
+                         ("k_dst3_scale (tau, FP32)" if fp32 else "k_dst_half (tau)"),
                          "bound": "hbm",
                          "achieved": round(bytes_b / (ms_stepb * 1e-3) / 1e9, 1),
                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -580,6 +581,7 @@ def main():
                         "ms_factor": round(float(np.mean([x["ms_factor"] for x in r["recs"]])), 3),
                         "iters": [x["iters"] for x in r["recs"][: len(alphas)]],
                         "ms_step_b": round(r["ms_stepb"], 4),
+                        "step_b_roofline": r["roofline_step_b"],
                         "spatial_solver": "tau (DST-I)" if f == "tau" else "exact LDL^T",
                         "rel_err_vs_oracle": err,
                         "speedup_vs_fp64": round(base["value"] / r["value"], 3)}

@@ -79,9 +79,13 @@ typedef struct {
   double true_rel_res;   /* ||F - A U|| / ||F|| recomputed at exit                             */
   double ms_setup;       /* plan setup time (g_k, symbols, lambda, factorisation)              */
   double ms_solve;       /* rfde_solve wall time (RHS + FGMRES + true residual)                */
-  double ms_pinv;        /* time inside preconditioner applications: the first one's time
-                            (HIP events) times the number of applications                      */
-  double ms_matvec;      /* time inside all-at-once matvecs, estimated the same way            */
+  int n_pinv;            /* preconditioner applications (steps (a)-(c)) made by the solve       */
+  int n_matvec;          /* all-at-once matvecs made by the solve (Arnoldi steps, the guess's
+                            residual and the true residual of every restart cycle)             */
+  double ms_pinv_est;    /* ESTIMATE of the time inside preconditioner applications: only the
+                            first application is timed (HIP events; timing every one would
+                            idle the GPU between launches), times n_pinv.  0 for batches       */
+  double ms_matvec_est;  /* ESTIMATE of the time inside matvecs, formed the same way            */
   int n_hist;            /* entries used in res_hist                                           */
   double res_hist[256];  /* estimated relative residual after each Arnoldi step (res_hist[0]=1)*/
 } rfde_stats;
@@ -372,6 +376,17 @@ int rfde_guess_assemble(int nsrc, int Nt, int Ks, int M, const float* g, const d
  * modes, times `factor` (training targets use 1/mode^2). */
 int rfde_project_sine(int Nt, int M, int Ks, const double* U, const double* S, double factor,
                       float* Y, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Measurement probe (not part of the method): the sustained matrix-core rate of one instruction
+ * form, from a kernel that issues only that instruction on register-resident operands (2048
+ * workgroups of 4 waves, 8 independent accumulator chains per wave, `iters` rounds), timed with
+ * HIP events after one warm-up launch.  kind 0: v_mfma_f64_16x16x4f64 (FP64, the factorisation),
+ * 1: v_mfma_f32_16x16x4f32 (FP32 factorisation), 2: v_mfma_f32_16x16x16bf16_1k (the guess
+ * network's output layer), 3: v_mfma_f32_16x16x32_bf16.  *tflops: host.  Synchronous; allocates
+ * a 2 MiB output buffer on the stream.  Errors: EINVAL (kind, iters outside 1..2^20, NULL), EHIP.
+ * ------------------------------------------------------------------------------------------ */
+int rfde_probe_mfma(int kind, int iters, double* tflops, void* stream);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,8 @@ class Opts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
                 ("true_rel_res", C.c_double), ("ms_setup", C.c_double), ("ms_solve", C.c_double),
-                ("ms_pinv", C.c_double), ("ms_matvec", C.c_double), ("n_hist", C.c_int),
+                ("n_pinv", C.c_int), ("n_matvec", C.c_int), ("ms_pinv_est", C.c_double),
+                ("ms_matvec_est", C.c_double), ("n_hist", C.c_int),
                 ("res_hist", C.c_double * 256)]
 
 
@@ -80,10 +81,13 @@ def lib() -> C.CDLL:
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+    # RFDE_LIBRARY names another build of the same library (e.g. one compiled with different
+    # launch shapes); the default is the in-tree build
+    path = os.environ.get("RFDE_LIBRARY") or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_2003_07020_amd.build` (needs hipcc, gfx950)")
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(path)
     vp, dp, ip, d, i = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_double, C.c_int
     L.rfde_opts_default.argtypes = [C.POINTER(Opts)]
     L.rfde_opts_default.restype = None
@@ -116,7 +120,8 @@ def lib() -> C.CDLL:
     L.rfde_batch_wave_of.argtypes = [vp, i]
     L.rfde_batch_get_info.argtypes = [vp, C.POINTER(BatchInfo)]
     L.rfde_batch_destroy.argtypes = [vp]
-    for name in ("rfde_gk", "rfde_plan_create_1d", "rfde_plan_create_2d", "rfde_plan_destroy",
+    L.rfde_probe_mfma.argtypes = [i, i, C.POINTER(d), vp]
+    for name in ("rfde_probe_mfma", "rfde_gk", "rfde_plan_create_1d", "rfde_plan_create_2d", "rfde_plan_destroy",
                  "rfde_plan_get_info", "rfde_plan_export", "rfde_build_rhs", "rfde_apply_A",
                  "rfde_pinv_step_a", "rfde_pinv_step_b", "rfde_pinv_step_c", "rfde_apply_Pinv",
                  "rfde_solve", "rfde_plan_autotune", "rfde_plan_set_variants", "rfde_batch_create", "rfde_batch_solve", "rfde_batch_set_grid_caps", "rfde_batch_set_autotune",

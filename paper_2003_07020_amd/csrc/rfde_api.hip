@@ -467,7 +467,7 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
   std::memset(&loc, 0, sizeof(loc));
   // Only the first preconditioner application and the first matvec of a solve are timed (an
   // event pair in the stream costs a few microseconds of idle GPU per step); the reported
-  // totals are those times multiplied by the number of applications.
+  // estimates are those times multiplied by the number of applications.
   float t_pinv = -1.f, t_mv = -1.f;
   int n_pinv = 0, n_mv = 0;
 
@@ -610,9 +610,11 @@ int rfde_solve(rfde_plan plan, const double* u0, const double* f, const double* 
   loc.true_rel_res = rel;
   loc.converged = rel <= tol ? 1 : 0;
   loc.ms_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
-  loc.ms_pinv = n_pinv > 0 ? (double)t_pinv * n_pinv : 0.0;
+  loc.n_pinv = n_pinv;
+  loc.n_matvec = n_mv;
+  loc.ms_pinv_est = n_pinv > 0 ? (double)t_pinv * n_pinv : 0.0;
   loc.ms_setup = p.ms_setup;
-  loc.ms_matvec = n_mv > 0 ? (double)t_mv * n_mv : 0.0;
+  loc.ms_matvec_est = n_mv > 0 ? (double)t_mv * n_mv : 0.0;
   if (stats) *stats = loc;
   return loc.converged ? RFDE_OK : RFDE_ENOTCONV;
 }

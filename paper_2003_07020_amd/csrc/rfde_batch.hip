@@ -584,6 +584,7 @@ int solve_wave(rfde_batch_& B, const std::vector<int>& idx, const double* const*
   for (int k = 0; k < cnt; ++k) {
     rfde_stats& s = loc[k];
     s.iters = total[k];
+    s.n_pinv = total[k];
     s.true_rel_res = failed[k] ? NAN : rel[k];
     s.converged = (!failed[k] && rel[k] <= o.tol) ? 1 : 0;
     s.ms_setup = ms_setup;

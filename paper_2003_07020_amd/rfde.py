@@ -52,19 +52,35 @@ def gk(alpha: float, n: int) -> torch.Tensor:
     return g
 
 
+def probe_mfma(kind: int, iters: int = 4096) -> float:
+    """Sustained matrix-core TFLOP/s of one instruction form (rfde_probe_mfma): kind 0 FP64
+    16x16x4, 1 FP32 16x16x4, 2 BF16 16x16x16, 3 BF16 16x16x32."""
+    out = C.c_double(0.0)
+    L.check(L.lib().rfde_probe_mfma(kind, iters, C.byref(out), _stream()), "rfde_probe_mfma")
+    return out.value
+
+
 @dataclass
 class SolveStats:
-    """Per-solve statistics (rfde_stats).  ms_pinv / ms_matvec: the first application's time
-    (HIP events) times the number of applications; ms_solve is wall time."""
+    """Per-solve statistics (rfde_stats).  ms_pinv_est / ms_matvec_est are estimates: the first
+    application's time (HIP events) times n_pinv / n_matvec; ms_solve is wall time."""
     iters: int
     restarts: int
     converged: bool
     true_rel_res: float
     ms_setup: float
     ms_solve: float
-    ms_pinv: float
-    ms_matvec: float
+    n_pinv: int
+    n_matvec: int
+    ms_pinv_est: float
+    ms_matvec_est: float
     res_hist: list
+
+    @classmethod
+    def from_c(cls, st):
+        return cls(st.iters, st.restarts, bool(st.converged), st.true_rel_res, st.ms_setup,
+                   st.ms_solve, st.n_pinv, st.n_matvec, st.ms_pinv_est, st.ms_matvec_est,
+                   [st.res_hist[k] for k in range(st.n_hist)])
 
 
 class Plan:
@@ -198,9 +214,7 @@ class Plan:
         allow = (L.RFDE_OK, L.RFDE_ENOTCONV) if allow_notconv else (L.RFDE_OK,)
         rc = L.check(L.lib().rfde_solve(self._h, _ptr(u0), _ptr(f), _ptr(U_init), _ptr(U), tol,
                                         C.byref(st)), "rfde_solve", allow)
-        stats = SolveStats(st.iters, st.restarts, bool(st.converged), st.true_rel_res,
-                           st.ms_setup, st.ms_solve, st.ms_pinv, st.ms_matvec,
-                           [st.res_hist[k] for k in range(st.n_hist)])
+        stats = SolveStats.from_c(st)
         return U, stats, rc
 
 
@@ -268,9 +282,7 @@ class Batch:
                                               P(*[t.data_ptr() for t in fs]),
                                               P(*[t.data_ptr() for t in outs]), st),
                      "rfde_batch_solve", allow)
-        stats = [SolveStats(s.iters, s.restarts, bool(s.converged), s.true_rel_res, s.ms_setup,
-                            s.ms_solve, s.ms_pinv, s.ms_matvec,
-                            [s.res_hist[k] for k in range(s.n_hist)]) for s in st]
+        stats = [SolveStats.from_c(s) for s in st]
         return outs, stats, rc
 
 

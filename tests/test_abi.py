@@ -89,3 +89,40 @@ def test_batch_rejects_invalid_arguments_without_device():
     assert L.rfde_batch_create(C.byref(h), 1, arr, C.byref(o), 0, None) == capi.RFDE_EUNSUPPORTED
     assert L.rfde_batch_solve(None, None, None, None, None) == capi.RFDE_EINVAL
     assert L.rfde_batch_destroy(None) == capi.RFDE_OK
+
+
+def _c_layout(struct, fields):
+    """sizeof and offsetof of a header struct, from a C program compiled with the host gcc."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    body = "".join(f'  printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src = (f'#include <stdio.h>\n#include <stddef.h>\n#include "rfde.h"\nint main(void) {{\n'
+           f'  printf("%zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("struct,pyname", [("rfde_opts", "Opts"), ("rfde_stats", "Stats"),
+                                           ("rfde_plan_info", "PlanInfo"),
+                                           ("rfde_instance", "Instance"),
+                                           ("rfde_batch_info", "BatchInfo")])
+def test_binding_structs_match_header_layout(struct, pyname):
+    # every field of the header's struct, in order, at the same offset, same total size
+    from paper_2003_07020_amd import capi
+    py = getattr(capi, pyname)
+    names = [f for f, _ in py._fields_]
+    size, offs = _c_layout(struct, names)
+    assert C.sizeof(py) == size
+    assert [getattr(py, f).offset for f in names] == offs
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + struct + r"\s*;", src).group(1)
+    declared = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*(?:\[[^\]]*\])?\s*[;,]", body)
+    assert declared == names

@@ -351,6 +351,22 @@ size_t rfde_mlp_workspace_bytes(const rfde_mlp* m, int B);
 int rfde_mlp_forward(const rfde_mlp* m, const float* feats, int B, float* g, void* ws,
                      void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * that produce initial guesses, harnesses that forbid hipMalloc): rfde_mlp_forward without the
+ * workspace argument.  Same kernels and result as rfde_mlp_forward (bit for bit); the
+ * activations (phat, h1, h2 and h2 in BF16: B (Pin + H1 + H2) 4 + B H2 2 bytes, at most 180 KiB
+ * within the limits above) live in a fixed device array of rfde_mlp_forward_noalloc_max_bytes()
+ * = 256 KiB per GPU, held until the process ends.  Calls no allocator.  Every call on one GPU
+ * shares that array, so calls that overlap on one GPU (concurrent streams or host threads) race;
+ * calls in one stream are ordered and safe.  Errors: EINVAL as rfde_mlp_forward (and if the
+ * activations would exceed the array), EUNSUPPORTED for a device index >= 64, EHIP if the
+ * array's device address cannot be obtained.
+ */
+int rfde_mlp_forward_noalloc(const rfde_mlp* m, const float* feats, int B, float* g,
+                             void* stream);
+size_t rfde_mlp_forward_noalloc_max_bytes(void);
+
 /* Forward, loss (device float *loss), and the gradients of the loss in `grads` (flat FP32,
  * order W1, b1, W2, b2, W3t, b3); parameters are not changed. */
 int rfde_mlp_grads(const rfde_mlp* m, const float* feats, const float* y, int B, float* g,

@@ -7,6 +7,7 @@
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulate) with BF16 copies of W3t, h2 and dg, while the
 // weight gradient dW3t = dg^T h2 is formed in FP32 inside the Adam update.  Loss = mean (g - y)^2.
 #include <cmath>
+#include <mutex>
 
 #include "rfde_internal.hpp"
 
@@ -360,19 +361,27 @@ struct MlpWs {
   unsigned short *h2b, *dgb;
   double* part;
 };
-static MlpWs carve(const rfde_mlp* m, int B, void* ws) {
+static inline size_t carve_round(size_t bytes) { return (bytes + 63) & ~(size_t)63; }
+// Bytes of the forward pass's part of the workspace (phat, h1, h2, h2 in BF16), which carve()
+// places first.
+static size_t forward_ws_bytes(const rfde_mlp* m, int B) {
+  return carve_round((size_t)B * m->Pin * 4) + carve_round((size_t)B * m->H1 * 4) +
+         carve_round((size_t)B * m->H2 * 4) + carve_round((size_t)B * m->H2 * 2);
+}
+static MlpWs carve(const rfde_mlp* m, int B, void* ws, bool forward_only = false) {
   unsigned char* p = (unsigned char*)ws;
   auto take = [&](size_t bytes) {
     unsigned char* r = p;
-    p += (bytes + 63) & ~(size_t)63;
+    p += carve_round(bytes);
     return (void*)r;
   };
   const size_t nchunk = ((size_t)m->NOUT + KCH - 1) / KCH;
-  MlpWs w;
+  MlpWs w{};
   w.phat = (float*)take((size_t)B * m->Pin * 4);
   w.h1 = (float*)take((size_t)B * m->H1 * 4);
   w.h2 = (float*)take((size_t)B * m->H2 * 4);
   w.h2b = (unsigned short*)take((size_t)B * m->H2 * 2);
+  if (forward_only) return w;
   w.dg = (float*)take((size_t)B * m->NOUT * 4);
   w.dgb = (unsigned short*)take((size_t)B * m->NOUT * 2);
   w.dh2part = (float*)take(nchunk * B * m->H2 * 4);
@@ -404,6 +413,46 @@ int rfde_mlp_forward(const rfde_mlp* m, const float* feats, int B, float* g, voi
                      void* stream) {
   if (!mlp_ok(m, B) || !feats || !g || !ws) return RFDE_EINVAL;
   MlpWs w = carve(m, B, ws);
+  return mlp_forward_impl(m, feats, B, g, w, (hipStream_t)stream);
+}
+
+// ---- forward pass without a caller workspace ---------------------------------------------------
+// The activations live in `scratch`, a fixed device array of each GPU.  Host code never uses the
+// array's name as an address: its device address is looked up once per device with
+// hipGetSymbolAddress and kept in scratch_dev[].  Every call on one device shares the array, so
+// calls on that device must not overlap (they race); nothing in it needs clearing, since the
+// forward pass writes every activation before reading it.
+constexpr size_t MLP_SCRATCH_BYTES = 256 * 1024;
+constexpr int MLP_SCRATCH_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[MLP_SCRATCH_BYTES];
+static void* scratch_dev[MLP_SCRATCH_MAX_DEVICES];
+static std::mutex scratch_mu;
+
+static int scratch_ptr(void** out) {
+  int dev = -1;
+  RFDE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MLP_SCRATCH_MAX_DEVICES) return RFDE_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* ptr = nullptr;
+    RFDE_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return RFDE_EHIP;
+    scratch_dev[dev] = ptr;
+  }
+  *out = scratch_dev[dev];
+  return RFDE_OK;
+}
+
+size_t rfde_mlp_forward_noalloc_max_bytes(void) { return MLP_SCRATCH_BYTES; }
+
+int rfde_mlp_forward_noalloc(const rfde_mlp* m, const float* feats, int B, float* g,
+                             void* stream) {
+  if (!mlp_ok(m, B) || !feats || !g) return RFDE_EINVAL;
+  if (forward_ws_bytes(m, B) > MLP_SCRATCH_BYTES) return RFDE_EINVAL;
+  void* ptr = nullptr;
+  const int rc = scratch_ptr(&ptr);
+  if (rc != RFDE_OK) return rc;
+  MlpWs w = carve(m, B, ptr, /*forward_only=*/true);
   return mlp_forward_impl(m, feats, B, g, w, (hipStream_t)stream);
 }
 

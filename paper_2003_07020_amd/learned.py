@@ -43,6 +43,9 @@ def _bind():
     lib.rfde_mlp_workspace_bytes.argtypes = [C.POINTER(MlpStruct), C.c_int]
     lib.rfde_mlp_workspace_bytes.restype = C.c_size_t
     lib.rfde_mlp_forward.argtypes = [C.POINTER(MlpStruct), vp, C.c_int, vp, vp, vp]
+    lib.rfde_mlp_forward_noalloc.argtypes = [C.POINTER(MlpStruct), vp, C.c_int, vp, vp]
+    lib.rfde_mlp_forward_noalloc_max_bytes.argtypes = []
+    lib.rfde_mlp_forward_noalloc_max_bytes.restype = C.c_size_t
     lib.rfde_mlp_grads.argtypes = [C.POINTER(MlpStruct), vp, vp, C.c_int, vp, vp, vp, vp, vp]
     lib.rfde_mlp_train_step.argtypes = [C.POINTER(MlpStruct), vp, vp, C.c_int, vp, C.c_float,
                                         C.c_int, vp, vp, vp]
@@ -50,7 +53,7 @@ def _bind():
     lib.rfde_sine_table.argtypes = [C.c_int, C.c_int, vp, vp]
     lib.rfde_guess_assemble.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp]
     lib.rfde_project_sine.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, C.c_double, vp, vp]
-    for n in ("rfde_mlp_forward", "rfde_mlp_grads", "rfde_mlp_train_step", "rfde_f32_to_bf16",
+    for n in ("rfde_mlp_forward", "rfde_mlp_forward_noalloc", "rfde_mlp_grads", "rfde_mlp_train_step", "rfde_f32_to_bf16",
               "rfde_sine_table", "rfde_guess_assemble", "rfde_project_sine"):
         getattr(lib, n).restype = C.c_int
     return lib
@@ -108,6 +111,15 @@ class GuessNet:
         L.check(self.lib.rfde_mlp_forward(C.byref(self.s), _ptr(feats), B, _ptr(self.g),
                                           _ptr(self.ws), _stream()), "rfde_mlp_forward")
         return self.g[: B * self.NOUT].view(B, self.NOUT)
+
+    def forward_noalloc(self, feats: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """forward() through rfde_mlp_forward_noalloc (no workspace; the library's fixed device
+        array holds the activations).  out: float32 device tensor of B * NOUT entries."""
+        B = feats.shape[0]
+        self._refresh_struct()
+        L.check(self.lib.rfde_mlp_forward_noalloc(C.byref(self.s), _ptr(feats), B, _ptr(out),
+                                                  _stream()), "rfde_mlp_forward_noalloc")
+        return out[: B * self.NOUT].view(B, self.NOUT)
 
     def grads(self, feats, y):
         B = feats.shape[0]

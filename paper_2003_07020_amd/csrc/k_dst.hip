@@ -5,8 +5,9 @@
 //     2D: z2_n = (Qy kron Qx) diag(1 / (lambda_n + coef_x sigma^x_i + coef_y sigma^y_j)) (Qy kron Qx) z1_n.
 // A length-n DST-I is computed by a complex FFT of length P = 2(n+1) of the odd extension
 // (0, x_1..x_n, 0, -x_n..-x_1): FFT_k = -2i sum_j x_j sin(pi j k/(n+1)), hence
-// (Q x)_k = sqrt(2/(n+1)) (i/2) FFT_k.  P must be a power of two.  1D rows in FP64 with
-// P >= 512 take a complex FFT of length P / 2 instead (k_dst_half).
+// (Q x)_k = sqrt(2/(n+1)) (i/2) FFT_k.  P must be a power of two here (other lengths take the
+// chirp-z DST of k_dst_bs.hip).  1D rows in FP64 with P >= 512 take a complex FFT of length
+// P / 2 instead (k_dst_half).
 #include <type_traits>
 
 #include "buf_io.hpp"
@@ -564,6 +565,7 @@ static int tau_solve_t(const Plan& p, const void* zinv, void* zio) {
   const C* zin = (const C*)zinv;
   const bool f32 = std::is_same<C, float2>::value;
   if (p.dim == 1) {
+    if (p.bs[0].LB) return tau_solve_1d_bs<C>(p, zin, z);
     const int P = 2 * (p.M + 1);
     const C* tw = f32 ? (const C*)((double2*)p.twD + P) : (const C*)p.twD;
     RFDE_P_SWITCH(P, dst_1d, C>(p, zin, z, tw));
@@ -575,10 +577,15 @@ static int tau_solve_t(const Plan& p, const void* zinv, void* zio) {
   const double2* twd = p.twD;
   const C* twx = f32 ? (const C*)(twd + Px + Py) : (const C*)twd;
   const C* twy = f32 ? (const C*)((const float2*)(twd + Px + Py) + Px) : (const C*)(twd + Px);
+  // axes whose 2(n+1) is not a power of two take the chirp-z DST (k_dst_bs.hip)
   auto rows = [&]() -> int {
+    if (p.bs[0].LB) return tau_rows_2d_bs<C>(p, z);
     RFDE_P_SWITCH(Px, dst_rows, C, false>(p, z, p.nf * p.My, p.My, p.sigma, 0.0, twx));
   };
-  auto cols = [&]() -> int { RFDE_P_SWITCH(Py, dst_cols, C>(p, z, twy)); };
+  auto cols = [&]() -> int {
+    if (p.bs[1].LB) return tau_cols_2d_bs<C>(p, z);
+    RFDE_P_SWITCH(Py, dst_cols, C>(p, z, twy));
+  };
   int rc = rows();
   if (rc != RFDE_OK) return rc;
   rc = cols();

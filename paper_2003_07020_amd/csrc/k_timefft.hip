@@ -367,6 +367,33 @@ static int bs_kernel(const Plan& p) {
     default: return RFDE_EINVAL;                   \
   }
 
+template <int LB>
+static int bs_spectrum(int n, const double2* w, const double2* tw, double2* bhat, float2* bhat32,
+                       hipStream_t st) {
+  k_bs_kernel<LB><<<1, 256, 0, st>>>(n, w, tw, bhat, bhat32);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+int launch_bs_spectrum(int n, const double2* w, const double2* tw, int LB, double2* bhat,
+                       float2* bhat32, hipStream_t st) {
+  if (LB < 2 * n - 1) return RFDE_EINVAL;
+  switch (LB) {
+    case 8: return bs_spectrum<8>(n, w, tw, bhat, bhat32, st);
+    case 16: return bs_spectrum<16>(n, w, tw, bhat, bhat32, st);
+    case 32: return bs_spectrum<32>(n, w, tw, bhat, bhat32, st);
+    case 64: return bs_spectrum<64>(n, w, tw, bhat, bhat32, st);
+    case 128: return bs_spectrum<128>(n, w, tw, bhat, bhat32, st);
+    case 256: return bs_spectrum<256>(n, w, tw, bhat, bhat32, st);
+    case 512: return bs_spectrum<512>(n, w, tw, bhat, bhat32, st);
+    case 1024: return bs_spectrum<1024>(n, w, tw, bhat, bhat32, st);
+    case 2048: return bs_spectrum<2048>(n, w, tw, bhat, bhat32, st);
+    case 4096: return bs_spectrum<4096>(n, w, tw, bhat, bhat32, st);
+    case 8192: return bs_spectrum<8192>(n, w, tw, bhat, bhat32, st);
+    default: return RFDE_EINVAL;
+  }
+}
+
 int launch_bluestein_setup(const Plan& p) {
   if (p.Lt == p.Nt) return RFDE_OK;
   k_bs_chirp<<<(p.Nt + 255) / 256, 256, 0, p.stream>>>(p.Nt, p.chirp, p.chirp32);

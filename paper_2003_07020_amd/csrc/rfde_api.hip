@@ -37,7 +37,10 @@ void free_plan(Plan* p) {
   void* bufs[] = {p->g,      p->sym,     p->twL,  p->twNt,   p->twNt32, p->chirp, p->chirp32,
                   p->bhat,   p->bhat32,  p->s,    p->lambda, p->sigma,  p->twD,   p->factors,
                   p->zf,     p->vbuf,    p->zbuf, p->wvec,   p->xvec,   p->Fvec,  p->red,
-                  p->redout,  p->set};
+                  p->redout,  p->set,    p->zt,
+                  p->bs[0].chirp, p->bs[0].chirp32, p->bs[0].khat, p->bs[0].khat32, p->bs[0].tw,
+                  p->bs[0].tw32,  p->bs[1].chirp,   p->bs[1].chirp32, p->bs[1].khat,
+                  p->bs[1].khat32, p->bs[1].tw,     p->bs[1].tw32};
   if (!p->arena)
     for (void* b : bufs) dev_free(b);
   if (p->hred) (void)hipHostFree(p->hred);
@@ -72,8 +75,20 @@ size_t workspace_estimate(const Plan& p) {
   const size_t N = p.N();
   const size_t m = (size_t)p.opts.restart;
   const size_t csz = p.opts.precond_bits == 32 ? 8 : 16;
-  return (2 * m + 1 + 3) * N * 8 + (size_t)p.nf * p.S * csz + ((size_t)70 * 1024) * 8 +
-         (size_t)(p.L + p.Lx + p.Ly + 4 * p.Lt + 3 * p.Nt) * 16;
+  const bool bs = p.bs[0].LB || p.bs[1].LB;
+  return (2 * m + 1 + 3) * N * 8 + (size_t)p.nf * p.S * csz * (bs ? 2 : 1) +
+         ((size_t)70 * 1024) * 8 +
+         (size_t)(p.L + p.Lx + p.Ly + 4 * p.Lt + 3 * p.Nt + 2 * (p.bs[0].LB + p.bs[1].LB) +
+                  p.M + p.Mx + p.My + 4) * 24;
+}
+
+// Axes of a tau plan whose DST-I length n has 2(n+1) not a power of two take the chirp-z
+// route: record n and the cyclic length.
+static void plan_dst_axes(Plan* p) {
+  if (p->opts.spatial != RFDE_SPATIAL_TAU) return;
+  const int n0 = p->dim == 1 ? p->M : p->Mx;
+  if (!is_pow2(n0 + 1)) { p->bs[0].n = n0; p->bs[0].LB = dstbs_length(n0); }
+  if (p->dim == 2 && !is_pow2(p->My + 1)) { p->bs[1].n = p->My; p->bs[1].LB = dstbs_length(p->My); }
 }
 
 // Everything common to 1D and 2D plans once the sizes are known.  factor = false leaves the
@@ -106,6 +121,19 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
   const size_t csz = p->opts.precond_bits == 32 ? 8 : 16;
   RFDE_TRY(palloc(p, &p->zf, (size_t)p->nf * p->S * csz));
   ws += (size_t)p->nf * p->S * csz;
+  for (DstBsAxis& x : p->bs) {
+    if (!x.LB) continue;
+    RFDE_TRY(dalloc(p, &x.chirp, x.n + 1, &ws));
+    RFDE_TRY(dalloc(p, &x.chirp32, x.n + 1, &ws));
+    RFDE_TRY(dalloc(p, &x.khat, x.LB, &ws));
+    RFDE_TRY(dalloc(p, &x.khat32, x.LB, &ws));
+    RFDE_TRY(dalloc(p, &x.tw, x.LB, &ws));
+    RFDE_TRY(dalloc(p, &x.tw32, x.LB, &ws));
+    if (!p->zt) {
+      RFDE_TRY(palloc(p, &p->zt, (size_t)p->nf * p->S * csz));
+      ws += (size_t)p->nf * p->S * csz;
+    }
+  }
   const size_t N = p->N();
   const size_t m = (size_t)p->opts.restart;
   RFDE_TRY(dalloc(p, &p->vbuf, (m + 1) * N, &ws));
@@ -166,6 +194,8 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
       RFDE_TRY(launch_tau_sigma(p->g, p->Mx, p->twD, p->sigma, st));
       RFDE_TRY(launch_tau_sigma(p->g + p->Mx, p->My, p->twD + P0, p->sigma + p->Mx, st));
     }
+    for (int a = 0; a < 2; ++a)
+      if (p->bs[a].LB) RFDE_TRY(dstbs_setup_axis(*p, a));
   }
   RFDE_TRY(launch_twiddles(p->twNt, p->Lt, st));
   RFDE_TRY(launch_twiddles32(p->twNt32, p->Lt, st));
@@ -229,7 +259,7 @@ int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M,
   p->L = std::max(16, next_pow2(2 * M - 1));
   p->opts = o;
   p->stream = stream;
-  if (o.spatial == RFDE_SPATIAL_TAU && !is_pow2(M + 1)) return RFDE_EUNSUPPORTED;
+  plan_dst_axes(p);
   if (o.spatial == RFDE_SPATIAL_EXACT) {
     p->T = (M + TILE - 1) / TILE;
     p->Mp = p->T * TILE;
@@ -307,7 +337,6 @@ int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double 
       Mx > 4096 || My > 4096 || !nt_ok(Nt) || !(T > 0.0) || !opts_ok(o) ||
       !std::isfinite(alpha_x + alpha_y + kappa_x + kappa_y + ax + bx + ay + by + T))
     return RFDE_EINVAL;
-  if (!is_pow2(Mx + 1) || !is_pow2(My + 1)) return RFDE_EUNSUPPORTED;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return RFDE_ENOMEM;
   p->dim = 2;
@@ -325,6 +354,7 @@ int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double 
   p->Ly = std::max(16, next_pow2(2 * My - 1));
   p->opts = o;
   p->stream = (hipStream_t)hip_stream;
+  plan_dst_axes(p);
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RFDE_EHIP; }
   const int rc = plan_allocate_and_setup(p, true);
   if (rc != RFDE_OK) { free_plan(p); return rc; }

@@ -65,6 +65,18 @@ struct Arena {
   size_t size = 0, used = 0;
 };
 
+// Tables of a DST-I of length n done by Bluestein's chirp-z form (2(n+1) not a power of two):
+// chirp c_m (m = 0..n), twiddles and kernel transform of the cyclic length LB (0: not used).
+struct DstBsAxis {
+  int n = 0, LB = 0;
+  double2* chirp = nullptr;
+  float2* chirp32 = nullptr;
+  double2* khat = nullptr;
+  float2* khat32 = nullptr;
+  double2* tw = nullptr;
+  float2* tw32 = nullptr;
+};
+
 struct Plan {
   int dim = 1;
   int M = 0, Mx = 0, My = 0, S = 0;   // S = spatial unknowns per time level
@@ -105,6 +117,9 @@ struct Plan {
   double2* lambda = nullptr; // nf
   double* sigma = nullptr;   // tau eigenvalues (unscaled): 1D M; 2D Mx then My
   double2* twD = nullptr;    // DST twiddles for length 2(n+1) (tau solver)
+  DstBsAxis bs[2];           // tau solver, axes whose DST-I length n has 2(n+1) not a power of
+                             // two (1D: bs[0]; 2D: bs[0] x, bs[1] y)
+  void* zt = nullptr;        // nf x S complex: the chirp-z DST's first-phase results
   void* factors = nullptr;   // nf blocks x lower_tiles(T) x 4096 complex (c128 or c64)
   size_t factor_bytes = 0;
   BlockSet* set = nullptr;   // this plan's blocks as a one-family set (device)
@@ -184,6 +199,16 @@ int launch_factorize_set(const BlockSet& hs, const BlockSet* ds, int bits, int g
 int launch_trsv_set(const BlockSet& hs, const BlockSet* ds, const void* const* zin,
                     void* const* zout, int bits, int grid_cap, hipStream_t st);
 int launch_tau_solve(const Plan& p, const void* zin, void* zout);
+// DST-I of any length (k_dst_bs.hip): cyclic length, per-axis tables, and the tau solves.
+int dstbs_length(int n);
+int dstbs_setup_axis(const Plan& p, int axis);
+template <typename C> int tau_solve_1d_bs(const Plan& p, const C* zin, C* z);
+template <typename C> int tau_rows_2d_bs(const Plan& p, C* z);
+template <typename C> int tau_cols_2d_bs(const Plan& p, C* z);
+// bhat = DFT_{-1}(b) / LB of the cyclic kernel b_k = conj(w_k) (k < n), b_{LB-k} = conj(w_k)
+// (0 < k < n), LB a power of two in 8..8192 (k_timefft.hip).
+int launch_bs_spectrum(int n, const double2* w, const double2* tw, int LB, double2* bhat,
+                       float2* bhat32, hipStream_t st);
 int launch_export_factor(const Plan& p, int index, void* dst);
 
 // BLAS-1 (deterministic fixed-order reductions)

@@ -65,10 +65,10 @@ def test_invalid_arguments_rejected_without_device():
     assert L.rfde_apply_A(None, None, None) == capi.RFDE_EINVAL
     assert L.rfde_solve(None, None, None, None, None, 0.0, None) == capi.RFDE_EINVAL
     assert L.rfde_plan_destroy(None) == capi.RFDE_OK
-    # 2D tau solver needs Mx+1 and My+1 to be powers of two
-    rc = L.rfde_plan_create_2d(C.byref(h), 1.6, 1.4, 1.0, 1.0, 0.0, 1.0, 0.0, 1.0, 100, 255, 256,
+    # 2D grid sizes above 4096 per axis
+    rc = L.rfde_plan_create_2d(C.byref(h), 1.6, 1.4, 1.0, 1.0, 0.0, 1.0, 0.0, 1.0, 5000, 255, 256,
                                1.0, None, None)
-    assert rc == capi.RFDE_EUNSUPPORTED
+    assert rc == capi.RFDE_EINVAL
     assert L.rfde_strerror(capi.RFDE_ENAN).decode().startswith("non-finite")
 
 

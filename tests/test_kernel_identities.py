@@ -1,6 +1,7 @@
 """Identities the GPU kernels are built on, checked in plain numpy on the CPU (no GPU, no
-oracle): the half-length DST-I of the 1D tau solve and the factored Arnoldi basis of the
-two-sweep CGS2.  The GPU parity tests check the kernels themselves against the oracle."""
+oracle): the half-length DST-I of the 1D tau solve, the chirp-z DST-I of any length, and the
+factored Arnoldi basis of the two-sweep CGS2.  The GPU parity tests check the kernels themselves
+against the oracle."""
 import numpy as np
 import pytest
 
@@ -95,3 +96,39 @@ def test_factored_cgs2_basis():
     # the directions differ from classic CGS2's only by the unapplied second projection of
     # u_j, so the Hessenberg matrices agree to rounding level
     assert np.abs(H2 - H).max() < 1e-12 * np.abs(H).max()
+
+
+def _dst_chirp_z(x):
+    """The sine sums S_k = sum_j x_j sin(pi j k/(n+1)), k = 1..n, as the chirp-z DST-I kernel
+    forms them: S = (P - Q)/(2i) with P_k = c_k sum_j (x_j c_j) conj(c_{k-j}) and
+    Q_k = conj(c_k) sum_j (x_j conj(c_j)) c_{k-j}, c_m = exp(i pi (m^2 mod 4(n+1)) / (2(n+1))),
+    each a cyclic convolution of length LB >= 2n - 1 with the kernel transform Khat (that of
+    conj(c_m)) for P and conj(Khat[(LB - k) mod LB]) for Q."""
+    n = len(x)
+    LB = 8
+    while LB < 2 * n - 1:
+        LB *= 2
+    m = np.arange(n + 1)
+    c = np.exp(1j * np.pi * ((m * m) % (4 * (n + 1))) / (2.0 * (n + 1)))
+    b = np.zeros(LB, dtype=complex)
+    b[:n] = np.conj(c[:n])
+    b[LB - np.arange(1, n)] = np.conj(c[1:n])
+    Khat = np.fft.fft(b) / LB
+    a = np.zeros(LB, dtype=complex)
+    a[1:n + 1] = x * c[1:]
+    P = np.fft.ifft(np.fft.fft(a) * Khat) * LB
+    a2 = np.zeros(LB, dtype=complex)
+    a2[1:n + 1] = x * np.conj(c[1:])
+    K2 = np.conj(Khat[(LB - np.arange(LB)) % LB])
+    Q = np.fft.ifft(np.fft.fft(a2) * K2) * LB
+    k = np.arange(1, n + 1)
+    return ((P[k] * c[k]) - (Q[k] * np.conj(c[k]))) / 2j
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 59, 60, 100, 255, 1000, 2730, 4096])
+def test_chirp_z_dst(n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    ref = _sine_sums(x)
+    got = _dst_chirp_z(x)
+    assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref))) * np.log2(4 * n + 8)

@@ -10,8 +10,9 @@ The headline `value` is the FP64 form (mean ms per solve, setup included).  The 
 timed for the FP32-preconditioner form and reported under "forms", each with its error against
 the oracle's exact solution.  Prints one JSON line.  --gpus > 1 is not supported.
 
---kernels-only runs a short fixed sequence (a 2 GiB device copy for counter calibration, one
-plan setup, three preconditioner applications and three matvecs) for profiler runs.
+--kernels-only runs a short fixed sequence for profiler runs (a 1 GiB device copy for counter
+calibration, the MFMA probes, and per form one plan setup, three preconditioner applications and
+three matvecs; one forward and training step of the guess network).
 """
 from __future__ import annotations
 
@@ -61,7 +62,7 @@ def workload(name):
 
 
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "traffic_kernels_1d_M4095_Nt1024_fp64.md")
+                               "pmc_kernels_only_1d_M4095_Nt1024_2d_255x255_Nt256.md")
 
 
 def pmc_traffic():
@@ -543,25 +544,56 @@ def measure_small(args, dev):
 
 
 def kernels_only(W, dev):
+    """A short fixed sequence for profiler runs (kernel trace, PMC counters): a 1 GiB device
+    copy (calibration of the byte counters), the matrix-core probes, then per form one plan setup
+    and three (P^-1, matvec) pairs: FP64 exact, FP32 exact, FP64 tau at the 1D workload, the 2D
+    workload in FP64 and FP32; and one forward and one training step of the guess network at
+    its benchmark shape (M = 1023, N_t = 512, Ks = 64, batch 32)."""
     import torch
 
-    from paper_2003_07020_amd.rfde import Plan
-    from rfde_workloads import gen1d
+    from paper_2003_07020_amd.rfde import Plan, probe_mfma
+    from rfde_workloads import GRID_2D, LEARNED, gen1d, gen2d
     n = 1 << 27  # 2^27 doubles = 1 GiB each way: calibration copy of known size
     a = torch.ones(n, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
+    del a, b
+    for kind in range(4):
+        probe_mfma(kind, 4096)
     M, Nt = W["M"], W["Nt"]
-    p = Plan.create_1d(1.5, W["kappa"], 0.0, 1.0, M, Nt, W["T"])
     u0, f, _ = gen1d(W["seed"], M, Nt)
-    v = torch.from_numpy(f.ravel()).to(dev)
-    z = torch.empty_like(v)
-    for _ in range(3):
-        p.apply_Pinv(v, out=z)
-        p.apply_A(z, out=v)
+    for bits, spatial in ((64, "exact"), (32, "exact"), (64, "tau")):
+        p = Plan.create_1d(1.5, W["kappa"], 0.0, 1.0, M, Nt, W["T"], precond_bits=bits,
+                           spatial=spatial)
+        v = torch.from_numpy(f.ravel()).to(dev)
+        z = torch.empty_like(v)
+        for _ in range(3):
+            p.apply_Pinv(v, out=z)
+            p.apply_A(z, out=v)
+        torch.cuda.synchronize()
+        p.destroy()
+    G = GRID_2D
+    u0, f, _ = gen2d(G["seed"], G["Mx"], G["My"], G["Nt"], G["T"])
+    for bits in (64, 32):
+        p = Plan.create_2d(G["alpha_x"], G["alpha_y"], G["kappa_x"], G["kappa_y"], 0.0, 1.0, 0.0,
+                           1.0, G["Mx"], G["My"], G["Nt"], G["T"], precond_bits=bits)
+        v = torch.from_numpy(f.ravel()).to(dev)
+        z = torch.empty_like(v)
+        for _ in range(3):
+            p.apply_Pinv(v, out=z)
+            p.apply_A(z, out=v)
+        torch.cuda.synchronize()
+        p.destroy()
+    from paper_2003_07020_amd.learned import GuessNet
+    NOUT = LEARNED["nsrc"] * LEARNED["Nt"] * LEARNED["Ks"]
+    net = GuessNet(3, 128, 256, NOUT, [1.5, 0.0, 0.0], [0.25, 0.5, 1.0], seed=0)
+    g = torch.Generator(device=dev).manual_seed(1)
+    feats = torch.randn(32, 3, dtype=torch.float32, device=dev, generator=g)
+    y = torch.randn(32, NOUT, dtype=torch.float32, device=dev, generator=g)
+    net.forward(feats)
+    net.train_step(feats, y, 1e-3)
     torch.cuda.synchronize()
-    p.destroy()
     print(json.dumps({"kernels_only": True, "copy_bytes_each_way": n * 8, "M": M, "Nt": Nt}))
 
 
@@ -718,7 +750,11 @@ def main():
         out["forms"]["small"] = small
     if cpu is not None:
         out["cpu_baseline"] = cpu
-    out["peak_probes"] = peak_probes(dev)
+    out["peak_probes"] = probes = peak_probes(dev)
+    if out["roofline"] is not None and forms[0] == "fp64":
+        # the same launches against the sustained rate of the FP64 matrix-core instruction they
+        # issue (a kernel of nothing but v_mfma_f64_16x16x4f64), beside the published peak
+        out["roofline"]["peak_probe"] = probes["mfma_f64_16x16x4_TFLOP/s"]
     print(json.dumps(out), flush=True)
 
 

@@ -128,12 +128,13 @@ int rfde_gk(double alpha, int n, double* g, void* hip_stream);
  *   alpha in (1, 2], kappa > 0, b > a, 1 <= M <= 4096, T > 0, and N_t >= 2 either a power of
  *   two up to 8192 or any other count up to 4096 (its time DFTs then use Bluestein's chirp-z
  *   form with a power-of-two length >= 2 N_t - 1); opts may be NULL (defaults).
- *   RFDE_SPATIAL_TAU needs M + 1 a power of two.
+ *   RFDE_SPATIAL_TAU accepts every M: its DST-I runs as one FFT of length 2(M+1) when that is a
+ *   power of two, else by the chirp-z form (two cyclic convolutions of a power-of-two length
+ *   >= 2M - 1, and a work array of the half spectrum's size).
  * Memory: the factors take nb * T(T+1)/2 * 4096 complex entries (T = ceil(M/64); 16 bytes
  * each in FP64, 8 in FP32; nb = n_freq, or n_freq - 1 for an even N_t, whose real blocks 0 and
  * N_t/2 share one complex-sized block): 69.8 GB for M = 4095, N_t = 1024 in FP64.
- * Errors: EINVAL on any range violation; EUNSUPPORTED for TAU with M + 1 not a power of two;
- * ENOMEM if factors plus workspace exceed free device memory (checked before allocating);
+ * Errors: EINVAL on any range violation; ENOMEM if factors plus workspace exceed free device memory (checked before allocating);
  * EHIP on a runtime failure.  On error *plan is set to NULL.
  */
 int rfde_plan_create_1d(rfde_plan* plan, double alpha, double kappa, double a, double b, int M,
@@ -141,9 +142,10 @@ int rfde_plan_create_1d(rfde_plan* plan, double alpha, double kappa, double a, d
 
 /*
  * Create a 2D plan (eq. (4.1)-(4.5)): A = -(c_x T_x (along x) + c_y T_y (along y)),
- * c = kappa / h^alpha, h_x = (bx-ax)/(Mx+1), h_y = (by-ay)/(My+1); Mx, My in [1, 4096] with
- * Mx + 1 and My + 1 powers of two (else EUNSUPPORTED); step (b) uses the 2D tau/DST
- * diagonalisation (no factors are stored).  Other arguments as in rfde_plan_create_1d.
+ * c = kappa / h^alpha, h_x = (bx-ax)/(Mx+1), h_y = (by-ay)/(My+1); Mx, My in [1, 4096]; step
+ * (b) uses the 2D tau/DST diagonalisation (no factors are stored), each axis's DST-I as in the
+ * 1D tau solver (FFT of length 2(n+1) or the chirp-z form).  Other arguments as in
+ * rfde_plan_create_1d.
  */
 int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double kappa_x,
                         double kappa_y, double ax, double bx, double ay, double by, int Mx, int My,

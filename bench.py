@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--precond-bits", type=int, default=64, choices=[64, 32])
     ap.add_argument("--learned-train", type=int, default=625)
     ap.add_argument("--learned-epochs", type=int, default=600)
-    ap.add_argument("--learned-heldout", type=int, default=64)
+    ap.add_argument("--learned-heldout", type=int, default=1000)
     ap.add_argument("--learned-ks", type=int, default=64)
     ap.add_argument("--learned-h1", type=int, default=128)
     ap.add_argument("--learned-h2", type=int, default=256)
@@ -250,7 +250,9 @@ def measure_learned(args, dev):
     progress(f"learned: trained in {t_train:.1f} s")
     del Y
     rec = []
-    for i in range(args.learned_heldout):
+    # held-out instances (seeds 15000, 15001, ...), each solved from the zero start and from the
+    # learned guess (plan setup, guess inference and assembly, solve); one untimed warm-up first
+    for i in [0] + list(range(args.learned_heldout)):
         seed = LW["heldout_seed"] + i
         alpha, kappa, u0, f, c = wl.learned_instance(seed, M, Nt, T)
         u0d, fd = torch.from_numpy(u0).to(dev), torch.from_numpy(f.ravel()).to(dev)
@@ -260,15 +262,18 @@ def measure_learned(args, dev):
             p = Plan.create_1d(alpha, kappa, 0.0, 1.0, M, Nt, T, tol=1e-8)
             Ug = lg.guess(alpha, kappa, c) if use else None
             U, st, _ = p.solve(u0d, fd, U_init=Ug)
+            torch.cuda.synchronize()
             tb = time.perf_counter()
+            # res_hist[0]: the relative residual of the start (1 when the guess was discarded)
             r = dict(seed=seed, guess=use, ms=(tb - ta) * 1e3, iters=st.iters,
-                     true_rel_res=st.true_rel_res)
+                     true_rel_res=st.true_rel_res, res0=st.res_hist[0])
             if use:
                 r["guess_rel_err"] = float(torch.linalg.norm(Ug - U) / torch.linalg.norm(U))
             rec.append(r)
             p.destroy()
-    z = [r for r in rec if not r["guess"]][1:]   # first zero-guess solve includes warm-up
+    z = [r for r in rec if not r["guess"]][1:]   # drop the warm-up pair
     g = [r for r in rec if r["guess"]][1:]
+    saved = np.array([a["iters"] - b["iters"] for a, b in zip(z, g)])
     return {"workload": LW["name"], "M": M, "Nt": Nt, "Ks": Ks, "H1": args.learned_h1,
             "H2": args.learned_h2, "epochs": args.learned_epochs,
             "train_draws": args.learned_train, "train_solves": nsolve,
@@ -280,6 +285,13 @@ def measure_learned(args, dev):
             "zero_guess_iters": round(float(np.mean([r["iters"] for r in z])), 3),
             "learned_guess_iters": round(float(np.mean([r["iters"] for r in g])), 3),
             "guess_rel_err_median": float(np.median([r["guess_rel_err"] for r in g])),
+            "guess_rel_err_p90": float(np.percentile([r["guess_rel_err"] for r in g], 90)),
+            "guess_residual_median": float(np.median([r["res0"] for r in g])),
+            "guess_discarded_fraction": round(float(np.mean([r["res0"] >= 1.0 for r in g])), 4),
+            "iters_saved_mean": round(float(saved.mean()), 3),
+            "iters_saved_histogram": {str(k): int((saved == k).sum()) for k in sorted(set(saved))},
+            "all_converged": bool(all(r["true_rel_res"] <= 1e-8 for r in z + g)),
+            "heldout_seeds": [z[0]["seed"], z[-1]["seed"]],
             "speedup": round(float(np.mean([r["ms"] for r in z]) / np.mean([r["ms"] for r in g])), 3)}
 
 

@@ -81,10 +81,14 @@ __global__ void __launch_bounds__(NT) k_matvec_rows(const double* __restrict__ v
 // stage's upper half of inputs and the last stage's upper half of outputs are pruned at
 // compile time.  Rows are addressed through buffer descriptors whose range is the row (or
 // empty for a row past the end or a level before the first), so the hardware range check
-// replaces every bounds test: loads outside read zero and stores outside are dropped.  Row
-// pairs are dealt so that each XCD takes a contiguous range (the stencil's neighbouring levels
-// are then read from the same L2).
-template <int L, bool ONE_ROW_PER_LEVEL, int WAVES>
+// replaces every bounds test: loads outside read zero and stores outside are dropped.
+// A pair is the same spatial row (index y within a level of rows_per_level rows) at two
+// consecutive levels 2kp and 2kp + 1, pair q = y K2 + kp with K2 = ceil(N_t / 2): the BDF2
+// stencil of the pair then needs only the rows of levels 2kp - 1 and 2kp - 2, which are the
+// rows of the previous pair, read moments before by the same workgroup (NB consecutive pairs)
+// or by its neighbour in the same XCD (pairs are dealt so that each XCD takes a contiguous
+// range).
+template <int L, int WAVES>
 __global__ void __launch_bounds__(256, WAVES)
     k_matvec3(const double* __restrict__ v, double* __restrict__ y,
               const double* __restrict__ sym, const double2* __restrict__ tw, int n, int rows,
@@ -95,6 +99,8 @@ __global__ void __launch_bounds__(256, WAVES)
   const int pair0 = xcd_remap(blockIdx.x, gridDim.x) * E::NB;
   const int nbytes = n * 8;
   const int rpl = rows_per_level;
+  const int K2 = (rows / rpl + 1) / 2;
+  const int npairs = rpl * K2;
   // row r of v (or y) as a buffer; empty when r is outside [0, rows)
   auto row = [&](const double* base, int r) {
     const bool ok = r >= 0 && r < rows;
@@ -102,25 +108,25 @@ __global__ void __launch_bounds__(256, WAVES)
   };
   // Per stage-1 butterfly of this thread (one row pair each): the rows it reads and writes and
   // the BDF2 rows of C (eq. (2.12)): level 0: v_0; level k >= 1: 3/2 v_k - 2 v_{k-1} + 1/2
-  // v_{k-2} (at level 1 the v_{k-2} term reads zero through an empty descriptor).
+  // v_{k-2} (missing levels read zero through empty descriptors).
   struct Rows {
-    __amdgpu_buffer_rsrc_t a, b, a1, b1, a2, b2, ya, yb;
-    double ca, cb;
+    __amdgpu_buffer_rsrc_t a, b, a1, a2, ya, yb;
+    double ca;
   };
   Rows rs[E::B1];
 #pragma unroll
   for (int b = 0; b < E::B1; ++b) {
-    const int r0 = 2 * (pair0 + E::f_of_b1(b)), r1 = r0 + 1;
+    const int q = pair0 + E::f_of_b1(b);
+    // past the last pair: every row (and its stencil rows) lies before the first
+    const int r0 = q < npairs ? 2 * (q % K2) * rpl + q / K2 : -3 * rpl - 1;
+    const int r1 = r0 + rpl;
     rs[b].a = row(v, r0);
     rs[b].b = row(v, r1);
     rs[b].a1 = row(v, r0 - rpl);
-    rs[b].b1 = rpl == 1 ? rs[b].a : row(v, r1 - rpl);
     rs[b].a2 = row(v, r0 - 2 * rpl);
-    rs[b].b2 = rpl == 1 ? rs[b].a1 : row(v, r1 - 2 * rpl);
     rs[b].ya = row(y, r0);
     rs[b].yb = row(y, r1);
     rs[b].ca = r0 < rpl ? 1.0 : 1.5;
-    rs[b].cb = r1 < rpl ? 1.0 : 1.5;
   }
   auto load = [&](int b, int, int idx, int n1) -> double2 {
     if (n1 >= E::N1 / 2) return make_double2(0.0, 0.0);
@@ -136,11 +142,7 @@ __global__ void __launch_bounds__(256, WAVES)
     const Rows& r = rs[b];
     const double va = buf_load(r.a, idx), va1 = buf_load(r.a1, idx);
     const double s0 = r.ca * va - 2.0 * va1 + 0.5 * buf_load(r.a2, idx);
-    // one time level per row: the pair's rows are levels k, k+1 and share v_k, v_{k-1}
-    const double s1 = ONE_ROW_PER_LEVEL
-                          ? r.cb * buf_load(r.b, idx) - 2.0 * va + 0.5 * va1
-                          : r.cb * buf_load(r.b, idx) - 2.0 * buf_load(r.b1, idx) +
-                                0.5 * buf_load(r.b2, idx);
+    const double s1 = 1.5 * buf_load(r.b, idx) - 2.0 * va + 0.5 * va1;
     buf_store(r.ya, idx, s0 + c.x);
     buf_store(r.yb, idx, s1 + c.y);
   };
@@ -203,12 +205,9 @@ static int mv_rows(const Plan& p, const double* v, double* y, int n, int rows, i
   // waves costs a few spills but hides latency better (measured 35 vs 44 us at M = 4095).
   // L <= 512 fits four waves (128 registers) without spills.
   constexpr int WAVES = L >= 8192 ? 2 : (L <= 512 ? 4 : 1);
-  const int groups = ((rows + 1) / 2 + E::NB - 1) / E::NB;
-  if (rpl == 1)
-    k_matvec3<L, true, WAVES><<<groups, 256, 0, p.stream>>>(v, y, p.sym, p.twL, n, rows, 1, live);
-  else
-    k_matvec3<L, false, WAVES><<<groups, 256, 0, p.stream>>>(v, y, p.sym, p.twL, n, rows, rpl,
-                                                            live);
+  const int npairs = rpl * ((rows / rpl + 1) / 2);
+  const int groups = (npairs + E::NB - 1) / E::NB;
+  k_matvec3<L, WAVES><<<groups, 256, 0, p.stream>>>(v, y, p.sym, p.twL, n, rows, rpl, live);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

@@ -248,15 +248,17 @@ __device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __r
     acc3_finish<C, D>(a3, acc);
     return;
   }
-  // per thread: 4 entries of each operand chunk (KC*64 = 1024 = 4 x 256) and one d
+  // per thread: PER entries of each operand chunk (KC*64 = PER x 256) and one d
+  constexpr int PER = KC * TILE / 256;
+  static_assert(PER * 256 == KC * TILE && KC <= 256 && KC % 4 == 0, "chunk shape");
   const C* Arow = fac + tile_index(i, 0) * TILE_ELEMS;
   const C* Brow = fac + tile_index(j, 0) * TILE_ELEMS;
-  C ra[4], rb[4], rd;
+  C ra[PER], rb[PER], rd;
   auto gload = [&](int c) {
     const int k = c / (TILE / KC), c0 = (c % (TILE / KC)) * KC;
     const size_t off = (size_t)k * TILE_ELEMS + (size_t)c0 * TILE;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < PER; ++u) {
       ra[u] = Arow[off + tid + 256 * u];
       rb[u] = Brow[off + tid + 256 * u];
     }
@@ -264,7 +266,7 @@ __device__ __forceinline__ void tile_update_staged(WaveAcc<C>& acc, const C* __r
   };
   auto lstore = [&](int bsel) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < PER; ++u) {
       sb.A[bsel][tid + 256 * u] = ra[u];
       sb.B[bsel][tid + 256 * u] = rb[u];
     }

@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="1d_M4095_Nt1024",
                     choices=["1d_M4095_Nt1024", "1d_M63_Nt64"])
-    ap.add_argument("--forms", default="fp64,fp32,tau,learned,batched,2d,small")
+    ap.add_argument("--forms", default="fp64,fp32,tau,toeplitz,learned,batched,2d,small")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--alphas", default="")
     ap.add_argument("--pinv-reps", type=int, default=10)
@@ -180,14 +180,20 @@ def measure_form(bits, args, W, alphas, inputs, dev, spatial="exact"):
     n_real = 2 if Nt % 2 == 0 else 1
     flops_factor = ((nf - n_real) * (4.0 / 3.0) + n_real / 3.0) * float(M) ** 3
     ms_factor = float(np.mean([r["ms_factor"] for r in recs]))
-    achieved = flops_factor / (ms_factor * 1e-3) / 1e12 if ms_factor > 0 else None
+    achieved = flops_factor / (ms_factor * 1e-3) / 1e12 if ms_factor > 0 and spatial == "exact" \
+        else None
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     esz = 8 if fp32 else 16
     # exact: the LDL^T factors are streamed twice (forward and backward): M^2 entries of esz
     # bytes per complex block, half that per real block; tau: the half spectrum is read and
-    # written by the DST solves (2 x 16 B per entry)
-    bytes_b = ((nf - n_real) + 0.5 * n_real) * float(M) * M * esz if spatial == "exact" \
-        else 2.0 * nf * M * 16
+    # written by the DST solves (2 x 16 B per entry); toeplitz: the half spectrum read and
+    # written and the generators (first columns of the inverses) read once (3 x 16 B per entry)
+    if spatial == "exact":
+        bytes_b = ((nf - n_real) + 0.5 * n_real) * float(M) * M * esz
+    elif spatial == "toeplitz":
+        bytes_b = 3.0 * nf * M * 16
+    else:
+        bytes_b = 2.0 * nf * M * 16
     # step (b) is timed through the C ABI; for FP32 plans that call also converts c128 <-> c64
     # around the solves (about 0.1% of its bytes at this size).
     N = float(Nt) * M
@@ -215,7 +221,8 @@ def measure_form(bits, args, W, alphas, inputs, dev, spatial="exact"):
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": None},
         roofline_step_b={"kernel": "k_trsv" if spatial == "exact" else
-                         ("k_dst3_scale (tau, FP32)" if fp32 else "k_dst_half (tau)"),
+                         ("k_gs_apply1+k_gs_apply2 (Gohberg-Semencul)" if spatial == "toeplitz"
+                          else ("k_dst3_scale (tau, FP32)" if fp32 else "k_dst_half (tau)")),
                          "bound": "hbm",
                          "achieved": round(bytes_b / (ms_stepb * 1e-3) / 1e9, 1),
                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -664,7 +671,8 @@ def main():
         progress("small form done")
     forms = [f for f in forms if f not in ("learned", "batched", "2d", "small")]
     # fp64: the plain exact-LDL^T form; fp32: its FP32 preconditioner; tau: the paper's own step
-    # (b) (DST-I diagonalisation of the tau approximation, no factors), FP64
+    # (b) (DST-I diagonalisation of the tau approximation, no factors), FP64; toeplitz: the same
+    # exact step (b) as fp64 from O(M) generators per block instead of factors, FP64
     from paper_2003_07020_amd.rfde import release_cached_memory
     results = {}
     for f in forms:
@@ -672,7 +680,7 @@ def main():
         # steps then reuse (the library caches freed device blocks)
         release_cached_memory()
         results[f] = measure_form(32 if f == "fp32" else 64, args, W, alphas, inputs, dev,
-                                  spatial="tau" if f == "tau" else "exact")
+                                  spatial=f if f in ("tau", "toeplitz") else "exact")
         progress(f"form {f} done")
     a_mid = alphas[len(alphas) // 2]
     if not results:
@@ -713,7 +721,10 @@ def main():
                         "iters": [x["iters"] for x in r["recs"][: len(alphas)]],
                         "ms_step_b": round(r["ms_stepb"], 4),
                         "step_b_roofline": r["roofline_step_b"],
-                        "spatial_solver": "tau (DST-I)" if f == "tau" else "exact LDL^T",
+                        "spatial_solver": {"tau": "tau (DST-I)",
+                                           "toeplitz": "exact, Levinson-Durbin generators + "
+                                                       "Gohberg-Semencul (no factors)"}.get(
+                                               f, "exact LDL^T"),
                         "rel_err_vs_oracle": err,
                         "rel_err_vs_oracle_max": None if not err else max(err.values()),
                         "speedup_vs_fp64": round(base["value"] / r["value"], 3)}

@@ -58,8 +58,13 @@ typedef enum {
 /* Spatial solver used in preconditioner step (b). */
 typedef enum {
   RFDE_SPATIAL_EXACT = 0, /* 1D: dense LDL^T (no pivoting) of lambda_n I - tau A, MFMA updates */
-  RFDE_SPATIAL_TAU = 1    /* DST-I diagonalisation of the tau approximation (eq. (3.9)-(3.11),
+  RFDE_SPATIAL_TAU = 1,   /* DST-I diagonalisation of the tau approximation (eq. (3.9)-(3.11),
                              eq. (4.5)); the only choice in 2D                               */
+  RFDE_SPATIAL_TOEPLITZ = 2 /* 1D, FP64: the same exact solves as EXACT without factors: each
+                             lambda_n I - tau A is symmetric Toeplitz, so its inverse follows
+                             from its first column (Levinson-Durbin recursion at setup, O(M^2)
+                             per block) by the Gohberg-Semencul formula, applied as four
+                             triangular Toeplitz products by FFT of length L               */
 } rfde_spatial;
 
 typedef struct {
@@ -69,7 +74,8 @@ typedef struct {
   double circ_eps;     /* circulant parameter in (0, 1]; <= 0 selects min(0.5, 0.5 tau)        */
   int precond_bits;    /* 64: FP64 preconditioner; 32: FP32/complex64 preconditioner (time FFTs
                           and shifted solves) inside the FP64 outer iteration. Default 64        */
-  int spatial;         /* rfde_spatial. Default RFDE_SPATIAL_EXACT in 1D (TAU is forced in 2D)  */
+  int spatial;         /* rfde_spatial. Default RFDE_SPATIAL_EXACT in 1D (TAU is forced in 2D);
+                          TOEPLITZ needs precond_bits = 64 (else EUNSUPPORTED)                */
 } rfde_opts;
 
 typedef struct {
@@ -103,7 +109,8 @@ typedef struct {
   size_t workspace_bytes;/* other device bytes held by the plan                                */
   int precond_bits, spatial;
   double ms_setup;       /* wall time of rfde_plan_create_* (all setup steps, synchronised)   */
-  double ms_factor;      /* device time of the factorisation launches (HIP events), 0 if none */
+  double ms_factor;      /* device time of the factorisation launches (HIP events; TOEPLITZ: the
+                            Levinson-Durbin recursions and generator transforms), 0 if none */
 } rfde_plan_info;
 
 /* Fill *o with the defaults listed above. */
@@ -173,8 +180,10 @@ typedef enum {
   RFDE_EXPORT_FACTOR = 4,  /* factor of block `index`: Mp*Mp c128 (FP32 plans: complex64) dense
                               row-major matrix holding unit-lower L (strict lower part) and D
                               (diagonal) with B = L D L^T; upper part zero                      */
-  RFDE_EXPORT_TAU_SIGMA = 5/* tau eigenvalues sigma_i of T (eq. (3.10)), unscaled: M doubles
+  RFDE_EXPORT_TAU_SIGMA = 5,/* tau eigenvalues sigma_i of T (eq. (3.10)), unscaled: M doubles
                               (2D: Mx then My); plans with spatial = TAU only, else EINVAL    */
+  RFDE_EXPORT_TOEPLITZ_X = 6/* first column of (lambda_n I + coef T)^{-1} for n = index: M c128;
+                              plans with spatial = TOEPLITZ only, else EINVAL                 */
 } rfde_export_what;
 
 /* Copy plan data into the device buffer dst (sizes above).  index: block for FACTOR.  async. */

@@ -17,8 +17,10 @@ RFDE_EUNSUPPORTED = -5
 
 SPATIAL_EXACT = 0
 SPATIAL_TAU = 1
+SPATIAL_TOEPLITZ = 2
 
-EXPORT_GK, EXPORT_SYMBOL, EXPORT_LAMBDA, EXPORT_SCALE, EXPORT_FACTOR, EXPORT_TAU_SIGMA = range(6)
+(EXPORT_GK, EXPORT_SYMBOL, EXPORT_LAMBDA, EXPORT_SCALE, EXPORT_FACTOR, EXPORT_TAU_SIGMA,
+ EXPORT_TOEPLITZ_X) = range(7)
 
 
 class Opts(C.Structure):

@@ -1,0 +1,264 @@
+// Preconditioner step (b), exact 1D variant without factors: every shifted block
+//     B_n = lambda_n I + coef T,   T[r][c] = g_|r-c|   (eq. (3.5))
+// is itself a symmetric Toeplitz matrix (complex, since lambda_n is), so its inverse is fixed by
+// one vector, the first column x = B_n^{-1} e_0, through the Gohberg-Semencul formula for
+// symmetric Toeplitz matrices:
+//     B^{-1} = (L(x) L(x)^T - L(u) L(u)^T) / x_0,   u = (0, x_{n-1}, ..., x_1),
+// with L(v) the lower-triangular Toeplitz matrix of first column v.  Setup computes x for every
+// frequency by the Levinson-Durbin recursion (O(M^2) per block instead of the O(M^3)
+// factorisation) and keeps its DFT; each application is four products with triangular Toeplitz
+// matrices, each a truncated linear convolution done by FFT of the circulant-embedding length L.
+//
+// Durbin's recursion on the normalised matrix R = B / t_0 (t_0 = lambda_n + coef g_0,
+// r_k = coef g_k / t_0): y^(1) = -r_1; for k = 1..n-2: beta <- (1 - a^2) beta,
+// a = -(r_{k+1} + sum_{i=1}^{k} r_{k+1-i} y_i) / beta, y_i <- y_i + a y_{k+1-i} (i <= k),
+// y_{k+1} = a; then x = gamma / t_0 (1, y), gamma = 1 / (1 + sum_i r_i y_i).  No conjugation:
+// B is complex symmetric, not Hermitian.  Every leading principal submatrix is nonsingular
+// (the Hermitian part Re(lambda_n) I + coef T is positive definite for eps < 1), so the
+// recursion does not break down.
+//
+// Products: L(v) w is the first n entries of the cyclic convolution of v and w padded to L
+// (L >= 2n - 1); L(v)^T w = J L(v) J w with J the reversal.  With X = DFT(x) (padded),
+// DFT(u)_k = w^{nk} (X_{-k} - x_0), w = exp(-2 pi i / L), so only X is stored.  One application:
+//     p = J L(x) J b,  q = J L(u) J b         (launch 1: two transform pairs on J b)
+//     z = (L(x) p - L(u) q) / x_0              (launch 2: two transform pairs)
+#include "fft_lds.hpp"
+#include "rfde_internal.hpp"
+
+namespace rfde {
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double den = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+
+// One workgroup per frequency n: x[n][0..M-1] = first column of B_n^{-1}.  y lives in LDS;
+// the dot product of each step is reduced in a fixed order (per-thread strided sums, wave
+// shuffles, then the four wave totals), so the result does not depend on scheduling.
+constexpr int LEV_NT = 256;
+__global__ void __launch_bounds__(LEV_NT) k_levinson(const double* __restrict__ g, double coef,
+                                                     const double2* __restrict__ lambda, int M,
+                                                     double2* __restrict__ xgen) {
+  extern __shared__ double2 y[];         // M - 1 entries (y[i-1] holds y_i)
+  __shared__ double2 part[LEV_NT / 64];
+  const int n = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const double2 lam = lambda[n];
+  const double2 t0 = make_double2(lam.x + coef * g[0], lam.y);
+  const double2 it0 = cdiv(make_double2(1.0, 0.0), t0);
+  // r_k = (coef g_k) / t_0 = rs * g_k
+  const double2 rs = make_double2(coef * it0.x, coef * it0.y);
+  double2* out = xgen + (size_t)n * M;
+  if (M == 1) {
+    if (t == 0) out[0] = it0;
+    return;
+  }
+  auto r = [&](int k) { const double gk = g[k]; return make_double2(rs.x * gk, rs.y * gk); };
+  // block sum of a per-thread complex value, identical in every thread
+  auto block_sum = [&](double2 v) -> double2 {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      v.x += __shfl_xor(v.x, m);
+      v.y += __shfl_xor(v.y, m);
+    }
+    if (lane == 0) part[w] = v;
+    __syncthreads();
+    double2 s = part[0];
+#pragma unroll
+    for (int q = 1; q < LEV_NT / 64; ++q) s = cadd(s, part[q]);
+    __syncthreads();  // part is reused by the next sum
+    return s;
+  };
+  double2 a = r(1);
+  a = make_double2(-a.x, -a.y);
+  if (t == 0) y[0] = a;
+  double2 beta = make_double2(1.0, 0.0);
+  __syncthreads();
+  for (int k = 1; k <= M - 2; ++k) {
+    beta = cmul(make_double2(1.0 - (a.x * a.x - a.y * a.y), -2.0 * a.x * a.y), beta);
+    // sum_{i=1}^{k} g_{k+1-i} y_i (then times rs), plus r_{k+1}
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = 1 + t; i <= k; i += LEV_NT) {
+      const double gi = g[k + 1 - i];
+      const double2 yi = y[i - 1];
+      acc.x = fma(gi, yi.x, acc.x);
+      acc.y = fma(gi, yi.y, acc.y);
+    }
+    const double2 sg = block_sum(acc);
+    const double2 s = cadd(cmul(rs, make_double2(sg.x + g[k + 1], sg.y)), make_double2(0.0, 0.0));
+    a = cdiv(s, beta);
+    a = make_double2(-a.x, -a.y);
+    // y_i <- y_i + a y_{k+1-i}, pairs (i, k+1-i) updated together by one thread
+    for (int i = 1 + t; 2 * i <= k + 1; i += LEV_NT) {
+      const int j = k + 1 - i;
+      const double2 yi = y[i - 1], yj = y[j - 1];
+      if (i == j) {
+        y[i - 1] = cadd(yi, cmul(a, yi));
+      } else {
+        y[i - 1] = cadd(yi, cmul(a, yj));
+        y[j - 1] = cadd(yj, cmul(a, yi));
+      }
+    }
+    if (t == 0) y[k] = a;
+    __syncthreads();
+  }
+  // gamma = 1 / (1 + sum_{i=1}^{M-1} r_i y_i)
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i = 1 + t; i <= M - 1; i += LEV_NT) {
+    const double gi = g[i];
+    const double2 yi = y[i - 1];
+    acc.x = fma(gi, yi.x, acc.x);
+    acc.y = fma(gi, yi.y, acc.y);
+  }
+  const double2 sg = block_sum(acc);
+  const double2 den = cadd(make_double2(1.0, 0.0), cmul(rs, sg));
+  const double2 sc = cdiv(it0, den);  // gamma / t_0
+  if (t == 0) out[0] = sc;
+  for (int i = 1 + t; i <= M - 1; i += LEV_NT) out[i] = cmul(sc, y[i - 1]);
+}
+
+// Xhat[n][k] = DFT_L(x[n] padded)_k / L, one workgroup per frequency.
+template <int L, int NT>
+__global__ void __launch_bounds__(NT) k_gs_spectrum(const double2* __restrict__ xgen, int M,
+                                                    const double2* __restrict__ tw,
+                                                    double2* __restrict__ xhat) {
+  __shared__ double2 buf[L];
+  const int n = blockIdx.x;
+  const double2* x = xgen + (size_t)n * M;
+  double2* X = xhat + (size_t)n * L;
+  auto load = [&](int, int idx) -> double2 { return idx < M ? x[idx] : make_double2(0.0, 0.0); };
+  auto store = [&](int, int k, double2 c) { X[k] = make_double2(c.x / L, c.y / L); };
+  fft_io<L, -1, NT, 1, L, false, true, true, 16>(buf, tw, load, store);
+}
+
+// Kernel transforms of the two generators at frequency index k (the tables hold 1/L):
+//   DFT(x)_k / L = X[k],   DFT(u)_k / L = w^{Mk} (X[-k] - x_0 / L).
+template <int L>
+__device__ __forceinline__ double2 gs_kernel(const double2* __restrict__ X,
+                                             const double2* __restrict__ tw, int M, double2 x0L,
+                                             int which, int k) {
+  if (which == 0) return X[k];
+  const double2 xm = X[(L - k) & (L - 1)];
+  const double2 wk = tw[(int)(((long long)M * k) & (L - 1))];
+  return cmul(wk, csub(xm, x0L));
+}
+
+// One transform pair per generator on a row held in LDS: out(idx) for idx < M receives the
+// first M entries of the cyclic convolution of the row (from load) with generator `which`.
+template <int L, int NT, typename Load, typename Store>
+__device__ __forceinline__ void gs_conv(double2* buf, const double2* __restrict__ tw,
+                                        const double2* __restrict__ X, int M, double2 x0L,
+                                        int which, Load& load, Store& store) {
+  auto mul = [&](int, int k, double2 c) { buf[k] = cmul(c, gs_kernel<L>(X, tw, M, x0L, which, k)); };
+  fft_io<L, -1, NT, 1, L, false, true, true, 16>(buf, tw, load, mul);
+  __syncthreads();
+  NoLoad nl;
+  fft_io<L, +1, NT, 1, L, false, false, true, 16>(buf, tw, nl, store);
+  __syncthreads();  // buf is reused by the next pair
+}
+
+// Launch 1: p = J L(x) J b, q = J L(u) J b for row n of b (one workgroup per row).
+template <int L, int NT>
+__global__ void __launch_bounds__(NT) k_gs_apply1(const double2* __restrict__ b,
+                                                  double2* __restrict__ P,
+                                                  double2* __restrict__ Q,
+                                                  const double2* __restrict__ xhat,
+                                                  const double2* __restrict__ xgen, int M,
+                                                  const double2* __restrict__ tw) {
+  __shared__ double2 buf[L];
+  const int n = blockIdx.x;
+  const double2* bn = b + (size_t)n * M;
+  const double2* X = xhat + (size_t)n * L;
+  const double2 x0 = xgen[(size_t)n * M];
+  const double2 x0L = make_double2(x0.x / L, x0.y / L);
+  auto load_rev = [&](int, int idx) -> double2 {
+    return idx < M ? bn[M - 1 - idx] : make_double2(0.0, 0.0);
+  };
+  double2* Pn = P + (size_t)n * M;
+  double2* Qn = Q + (size_t)n * M;
+  auto store_p = [&](int, int idx, double2 c) { if (idx < M) Pn[M - 1 - idx] = c; };
+  auto store_q = [&](int, int idx, double2 c) { if (idx < M) Qn[M - 1 - idx] = c; };
+  gs_conv<L, NT>(buf, tw, X, M, x0L, 0, load_rev, store_p);
+  gs_conv<L, NT>(buf, tw, X, M, x0L, 1, load_rev, store_q);
+}
+
+// Launch 2: z = (L(x) p - L(u) q) / x_0 for row n.  The second pair's store subtracts from the
+// value the same thread stored in the first (the store pattern of the last pass is fixed per
+// thread).
+template <int L, int NT>
+__global__ void __launch_bounds__(NT) k_gs_apply2(const double2* __restrict__ P,
+                                                  const double2* __restrict__ Q,
+                                                  double2* __restrict__ z,
+                                                  const double2* __restrict__ xhat,
+                                                  const double2* __restrict__ xgen, int M,
+                                                  const double2* __restrict__ tw) {
+  __shared__ double2 buf[L];
+  const int n = blockIdx.x;
+  const double2* X = xhat + (size_t)n * L;
+  const double2 x0 = xgen[(size_t)n * M];
+  const double2 x0L = make_double2(x0.x / L, x0.y / L);
+  const double2 ix0 = cdiv(make_double2(1.0, 0.0), x0);
+  const double2* Pn = P + (size_t)n * M;
+  const double2* Qn = Q + (size_t)n * M;
+  double2* zn = z + (size_t)n * M;
+  auto load_p = [&](int, int idx) -> double2 { return idx < M ? Pn[idx] : make_double2(0.0, 0.0); };
+  auto load_q = [&](int, int idx) -> double2 { return idx < M ? Qn[idx] : make_double2(0.0, 0.0); };
+  auto store1 = [&](int, int idx, double2 c) { if (idx < M) zn[idx] = c; };
+  auto store2 = [&](int, int idx, double2 c) {
+    if (idx < M) zn[idx] = cmul(csub(zn[idx], c), ix0);
+  };
+  gs_conv<L, NT>(buf, tw, X, M, x0L, 0, load_p, store1);
+  gs_conv<L, NT>(buf, tw, X, M, x0L, 1, load_q, store2);
+}
+
+template <int L> constexpr int gs_threads() { return L >= 2048 ? 512 : (L >= 256 ? 256 : 64); }
+
+template <int L>
+static int gs_setup_t(const Plan& p) {
+  constexpr int NT = gs_threads<L>();
+  k_gs_spectrum<L, NT><<<p.nf, NT, 0, p.stream>>>(p.gs_x, p.M, p.twL, p.gs_xhat);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+template <int L>
+static int gs_apply_t(const Plan& p, const double2* z1, double2* z2) {
+  constexpr int NT = gs_threads<L>();
+  k_gs_apply1<L, NT><<<p.nf, NT, 0, p.stream>>>(z1, p.gs_p, p.gs_q, p.gs_xhat, p.gs_x, p.M,
+                                                 p.twL);
+  RFDE_HIP(hipGetLastError());
+  k_gs_apply2<L, NT><<<p.nf, NT, 0, p.stream>>>(p.gs_p, p.gs_q, z2, p.gs_xhat, p.gs_x, p.M,
+                                                 p.twL);
+  RFDE_HIP(hipGetLastError());
+  return RFDE_OK;
+}
+
+#define RFDE_GSL_SWITCH(FN, ...)                 \
+  switch (p.L) {                                 \
+    case 16: return FN<16>(__VA_ARGS__);         \
+    case 32: return FN<32>(__VA_ARGS__);         \
+    case 64: return FN<64>(__VA_ARGS__);         \
+    case 128: return FN<128>(__VA_ARGS__);       \
+    case 256: return FN<256>(__VA_ARGS__);       \
+    case 512: return FN<512>(__VA_ARGS__);       \
+    case 1024: return FN<1024>(__VA_ARGS__);     \
+    case 2048: return FN<2048>(__VA_ARGS__);     \
+    case 4096: return FN<4096>(__VA_ARGS__);     \
+    case 8192: return FN<8192>(__VA_ARGS__);     \
+    default: return RFDE_EINVAL;                 \
+  }
+
+// Setup of the Toeplitz solver: generators by Levinson-Durbin, then their transforms.
+int launch_gs_setup(const Plan& p) {
+  const size_t lds = (size_t)(p.M > 1 ? p.M - 1 : 1) * sizeof(double2);
+  k_levinson<<<p.nf, LEV_NT, lds, p.stream>>>(p.g, p.coef, p.lambda, p.M, p.gs_x);
+  RFDE_HIP(hipGetLastError());
+  RFDE_GSL_SWITCH(gs_setup_t, p);
+}
+
+// z2_n = B_n^{-1} z1_n for every frequency (z1 may alias z2: launch 1 reads z1 and writes
+// only the work arrays; launch 2 writes z2).
+int launch_gs_apply(const Plan& p, const void* z1, void* z2) {
+  RFDE_GSL_SWITCH(gs_apply_t, p, (const double2*)z1, (double2*)z2);
+}
+
+}  // namespace rfde

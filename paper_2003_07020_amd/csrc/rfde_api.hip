@@ -37,7 +37,7 @@ void free_plan(Plan* p) {
   void* bufs[] = {p->g,      p->sym,     p->twL,  p->twNt,   p->twNt32, p->chirp, p->chirp32,
                   p->bhat,   p->bhat32,  p->s,    p->lambda, p->sigma,  p->twD,   p->factors,
                   p->zf,     p->vbuf,    p->zbuf, p->wvec,   p->xvec,   p->Fvec,  p->red,
-                  p->redout,  p->set,    p->zt,
+                  p->redout,  p->set,    p->zt,     p->gs_x,  p->gs_xhat, p->gs_p, p->gs_q,
                   p->bs[0].chirp, p->bs[0].chirp32, p->bs[0].khat, p->bs[0].khat32, p->bs[0].tw,
                   p->bs[0].tw32,  p->bs[1].chirp,   p->bs[1].chirp32, p->bs[1].khat,
                   p->bs[1].khat32, p->bs[1].tw,     p->bs[1].tw32};
@@ -76,7 +76,9 @@ size_t workspace_estimate(const Plan& p) {
   const size_t m = (size_t)p.opts.restart;
   const size_t csz = p.opts.precond_bits == 32 ? 8 : 16;
   const bool bs = p.bs[0].LB || p.bs[1].LB;
-  return (2 * m + 1 + 3) * N * 8 + (size_t)p.nf * p.S * csz * (bs ? 2 : 1) +
+  const size_t gs = p.opts.spatial == RFDE_SPATIAL_TOEPLITZ
+                        ? (size_t)p.nf * (3 * (size_t)p.M + p.L) * sizeof(double2) : 0;
+  return gs + (2 * m + 1 + 3) * N * 8 + (size_t)p.nf * p.S * csz * (bs ? 2 : 1) +
          ((size_t)70 * 1024) * 8 +
          (size_t)(p.L + p.Lx + p.Ly + 4 * p.Lt + 3 * p.Nt + 2 * (p.bs[0].LB + p.bs[1].LB) +
                   p.M + p.Mx + p.My + 4) * 24;
@@ -121,6 +123,12 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
   const size_t csz = p->opts.precond_bits == 32 ? 8 : 16;
   RFDE_TRY(palloc(p, &p->zf, (size_t)p->nf * p->S * csz));
   ws += (size_t)p->nf * p->S * csz;
+  if (p->opts.spatial == RFDE_SPATIAL_TOEPLITZ) {
+    RFDE_TRY(dalloc(p, &p->gs_x, (size_t)p->nf * p->M, &ws));
+    RFDE_TRY(dalloc(p, &p->gs_xhat, (size_t)p->nf * p->L, &ws));
+    RFDE_TRY(dalloc(p, &p->gs_p, (size_t)p->nf * p->M, &ws));
+    RFDE_TRY(dalloc(p, &p->gs_q, (size_t)p->nf * p->M, &ws));
+  }
   for (DstBsAxis& x : p->bs) {
     if (!x.LB) continue;
     RFDE_TRY(dalloc(p, &x.chirp, x.n + 1, &ws));
@@ -201,13 +209,18 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
   RFDE_TRY(launch_twiddles32(p->twNt32, p->Lt, st));
   RFDE_TRY(launch_bluestein_setup(*p));
   RFDE_TRY(launch_time_data(p->Nt, p->eps, p->s, p->lambda, st));
+  if (p->opts.spatial == RFDE_SPATIAL_TOEPLITZ) {
+    RFDE_HIP(hipEventRecord(p->ev[0], st));
+    RFDE_TRY(launch_gs_setup(*p));
+    RFDE_HIP(hipEventRecord(p->ev[1], st));
+  }
   if (p->factor_bytes && factor) {
     RFDE_HIP(hipEventRecord(p->ev[0], st));
     RFDE_TRY(launch_factorize(*p));
     RFDE_HIP(hipEventRecord(p->ev[1], st));
   }
   RFDE_HIP(hipStreamSynchronize(st));
-  if (p->factor_bytes && factor) {
+  if ((p->factor_bytes && factor) || p->opts.spatial == RFDE_SPATIAL_TOEPLITZ) {
     float t = 0.f;
     RFDE_HIP(hipEventElapsedTime(&t, p->ev[0], p->ev[1]));
     p->ms_factor = t;
@@ -219,12 +232,14 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
 static bool opts_ok(const rfde_opts& o) {
   return o.tol > 0 && o.maxit >= 1 && o.restart >= 1 && o.restart <= 64 && o.circ_eps <= 1.0 &&
          (o.precond_bits == 64 || o.precond_bits == 32) &&
-         (o.spatial == RFDE_SPATIAL_EXACT || o.spatial == RFDE_SPATIAL_TAU);
+         (o.spatial == RFDE_SPATIAL_EXACT || o.spatial == RFDE_SPATIAL_TAU ||
+          o.spatial == RFDE_SPATIAL_TOEPLITZ);
 }
 
 // ---- steps ----
 static int pinv_step_b(const Plan& p, const void* z1, void* z2) {
   if (p.opts.spatial == RFDE_SPATIAL_EXACT) return launch_trsv(p, z1, z2);
+  if (p.opts.spatial == RFDE_SPATIAL_TOEPLITZ) return launch_gs_apply(p, z1, z2);
   return launch_tau_solve(p, z1, z2);
 }
 
@@ -260,6 +275,7 @@ int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M,
   p->opts = o;
   p->stream = stream;
   plan_dst_axes(p);
+  if (o.spatial == RFDE_SPATIAL_TOEPLITZ && o.precond_bits != 64) return RFDE_EUNSUPPORTED;
   if (o.spatial == RFDE_SPATIAL_EXACT) {
     p->T = (M + TILE - 1) / TILE;
     p->Mp = p->T * TILE;
@@ -414,6 +430,12 @@ int rfde_plan_export(rfde_plan plan, int what, int index, void* dst) {
     case RFDE_EXPORT_FACTOR:
       if (!p->factor_bytes || index < 0 || index >= p->nf) return RFDE_EINVAL;
       return launch_export_factor(*p, index, dst);
+    case RFDE_EXPORT_TOEPLITZ_X:
+      if (p->opts.spatial != RFDE_SPATIAL_TOEPLITZ || index < 0 || index >= p->nf)
+        return RFDE_EINVAL;
+      RFDE_HIP(hipMemcpyAsync(dst, p->gs_x + (size_t)index * p->M, p->M * sizeof(double2),
+                              hipMemcpyDeviceToDevice, st));
+      return RFDE_OK;
     case RFDE_EXPORT_TAU_SIGMA:
       if (p->opts.spatial != RFDE_SPATIAL_TAU) return RFDE_EINVAL;  // only tau plans hold sigma
       RFDE_HIP(hipMemcpyAsync(dst, p->sigma, gl * sizeof(double), hipMemcpyDeviceToDevice, st));

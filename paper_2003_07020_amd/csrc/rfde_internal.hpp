@@ -120,6 +120,12 @@ struct Plan {
   DstBsAxis bs[2];           // tau solver, axes whose DST-I length n has 2(n+1) not a power of
                              // two (1D: bs[0]; 2D: bs[0] x, bs[1] y)
   void* zt = nullptr;        // nf x S complex: the chirp-z DST's first-phase results
+  // Toeplitz (Gohberg-Semencul) solver: first columns of the inverses (nf x M), their DFTs of
+  // length L divided by L (nf x L), and the two intermediate products (nf x M each)
+  double2* gs_x = nullptr;
+  double2* gs_xhat = nullptr;
+  double2* gs_p = nullptr;
+  double2* gs_q = nullptr;
   void* factors = nullptr;   // nf blocks x lower_tiles(T) x 4096 complex (c128 or c64)
   size_t factor_bytes = 0;
   BlockSet* set = nullptr;   // this plan's blocks as a one-family set (device)
@@ -199,6 +205,9 @@ int launch_factorize_set(const BlockSet& hs, const BlockSet* ds, int bits, int g
 int launch_trsv_set(const BlockSet& hs, const BlockSet* ds, const void* const* zin,
                     void* const* zout, int bits, int grid_cap, hipStream_t st);
 int launch_tau_solve(const Plan& p, const void* zin, void* zout);
+// Toeplitz solver (k_gs.hip): setup (generators and their transforms) and step (b).
+int launch_gs_setup(const Plan& p);
+int launch_gs_apply(const Plan& p, const void* z1, void* z2);
 // DST-I of any length (k_dst_bs.hip): cyclic length, per-axis tables, and the tau solves.
 int dstbs_length(int n);
 int dstbs_setup_axis(const Plan& p, int axis);

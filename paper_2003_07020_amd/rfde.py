@@ -36,7 +36,8 @@ def opts(tol=1e-8, maxit=200, restart=30, circ_eps=0.0, precond_bits=64, spatial
     L.lib().rfde_opts_default(C.byref(o))
     o.tol, o.maxit, o.restart, o.circ_eps = tol, maxit, restart, circ_eps
     o.precond_bits = precond_bits
-    o.spatial = L.SPATIAL_EXACT if spatial == "exact" else L.SPATIAL_TAU
+    o.spatial = {"exact": L.SPATIAL_EXACT, "tau": L.SPATIAL_TAU,
+                 "toeplitz": L.SPATIAL_TOEPLITZ}[spatial]
     return o
 
 
@@ -183,6 +184,8 @@ class Plan:
         elif what == L.EXPORT_FACTOR:
             dt = torch.complex64 if i["precond_bits"] == 32 else torch.complex128
             t = torch.empty(i["Mp"] * i["Mp"], dtype=dt)
+        elif what == L.EXPORT_TOEPLITZ_X:
+            t = torch.empty(i["M"], dtype=torch.complex128)
         elif what == L.EXPORT_TAU_SIGMA:
             t = torch.empty(i["M"] if i["dim"] == 1 else i["Mx"] + i["My"], dtype=torch.float64)
         else:

@@ -198,3 +198,44 @@ def test_fp32_shifted_solves_sampled(big32):
             np.linalg.norm(B, 1) * np.linalg.norm(z2[n]) + np.linalg.norm(z1_ref[n]))
         print(f"fp32 alpha={alpha} n={n}: backward error {bwd:.2e}", flush=True)
         assert bwd < 0.25 * M * u32, (n, bwd)
+
+
+@pytest.fixture(scope="module", params=ALPHAS)
+def bigT(request):
+    # the factor-free exact step (b): Levinson-Durbin generators + Gohberg-Semencul solves
+    from paper_2003_07020_amd.rfde import Plan
+    alpha = request.param
+    banner(f"large toeplitz plan alpha={alpha} M={M} Nt={NT}")
+    p = Plan.create_1d(alpha, KAPPA, 0.0, 1.0, M, NT, T, tol=1e-10, spatial="toeplitz")
+    h, tau = aa.mesh(0.0, 1.0, M, T, NT)
+    yield alpha, p, h, tau, aa.jacobian_A(alpha, KAPPA, h, M), pc.default_eps(tau)
+    p.destroy()
+
+
+def test_toeplitz_shifted_solves_sampled(bigT):
+    # same bars as the LDL^T solves (test_shifted_solves_sampled): forward error within the
+    # conditioning, normwise backward error at the level of an order-M elimination
+    alpha, p, h, tau, A, eps = bigT
+    v = random_vector(25, NT * M).reshape(NT, M)
+    z1_ref = pc.step_a(v, eps)
+    z2 = to_host(p.step_b(to_dev(z1_ref.ravel()))).reshape(-1, M)
+    lam = pc.eigenvalues(NT, eps)
+    for n in (0, 1, 300, NT // 2):
+        B = pc.shifted_matrix(lam[n], A, tau)
+        ref = sla.lu_solve(sla.lu_factor(B), z1_ref[n])
+        assert rel_max(z2[n], ref) < 2e-8, n
+        bwd = np.linalg.norm(B @ z2[n] - z1_ref[n]) / (
+            np.linalg.norm(B, 1) * np.linalg.norm(z2[n]) + np.linalg.norm(z1_ref[n]))
+        print(f"toeplitz alpha={alpha} n={n}: backward error {bwd:.2e}", flush=True)
+        assert bwd < 1e-13, (n, bwd)
+
+
+def test_toeplitz_solve_full(bigT):
+    alpha, p, h, tau, A, eps = bigT
+    u0, f, Uref = oracle_march(alpha)
+    U, st, _ = p.solve(to_dev(u0), to_dev(f.ravel()), tol=1e-10)
+    err = rel_max(to_host(U).reshape(NT, M), Uref)
+    print(f"toeplitz alpha={alpha}: iters={st.iters} true_rel_res={st.true_rel_res:.2e} "
+          f"rel_err={err:.2e} ms_setup={p.info['ms_setup']:.1f}", flush=True)
+    assert st.converged and st.true_rel_res <= 1e-10
+    assert err < 1e-8

@@ -132,3 +132,63 @@ def test_chirp_z_dst(n):
     ref = _sine_sums(x)
     got = _dst_chirp_z(x)
     assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref))) * np.log2(4 * n + 8)
+
+
+def _durbin_first_column(t):
+    """First column of T^-1 for the complex symmetric Toeplitz T of first column t, by Durbin's
+    recursion on T / t_0 (no conjugation), as the setup kernel runs it."""
+    n = len(t)
+    if n == 1:
+        return np.array([1.0 / t[0]])
+    r = t[1:] / t[0]
+    y = np.zeros(n - 1, dtype=complex)
+    a = -r[0]
+    y[0] = a
+    beta = 1.0 + 0j
+    for k in range(1, n - 1):
+        beta = (1 - a * a) * beta
+        a = -(r[k] + np.dot(r[k - 1::-1][:k], y[:k])) / beta
+        yk = y[:k].copy()
+        y[:k] = yk + a * yk[::-1]
+        y[k] = a
+    gamma = 1.0 / (1.0 + np.dot(r, y))
+    return gamma / t[0] * np.concatenate([[1.0], y])
+
+
+def _gohberg_semencul_apply(x, b, L):
+    """T^-1 b = (L(x) L(x)^T b - L(u) L(u)^T b) / x_0, u = (0, x_{n-1}, .., x_1), with the four
+    triangular Toeplitz products as truncated cyclic convolutions of length L, the transform of
+    u taken from that of x (DFT(u)_k = w^{nk} (X_{-k} - x_0)), and L(v)^T = J L(v) J."""
+    n = len(x)
+    X = np.fft.fft(np.concatenate([x, np.zeros(L - n)])) / L
+    k = np.arange(L)
+    U = np.exp(-2j * np.pi * ((n * k) % L) / L) * (X[(L - k) % L] - x[0] / L)
+
+    def conv(v, S):
+        V = np.fft.fft(np.concatenate([v, np.zeros(L - len(v))]))
+        return (np.fft.ifft(V * S) * L)[:n]
+
+    p = conv(b[::-1], X)[::-1]
+    q = conv(b[::-1], U)[::-1]
+    return (conv(p, X) - conv(q, U)) / x[0]
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 63, 100, 511])
+def test_durbin_gohberg_semencul(n):
+    # a symmetric positive definite Toeplitz T (first column from a positive spectral density)
+    # plus a complex shift with positive real part: B = lam I + T, complex symmetric
+    rng = np.random.default_rng(n)
+    th = rng.uniform(0, np.pi, 8)
+    wts = rng.uniform(0.1, 1.0, 8)
+    t = np.array([np.sum(wts * np.cos(k * th)) for k in range(n)], dtype=complex)
+    t[0] += 0.05 + 0.3j
+    B = np.array([[t[abs(i - j)] for j in range(n)] for i in range(n)])
+    x = _durbin_first_column(t)
+    assert np.allclose(B @ x, np.eye(n)[:, 0], atol=1e-12)
+    L = 16
+    while L < 2 * n - 1:
+        L *= 2
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    z = _gohberg_semencul_apply(x, b, L)
+    ref = np.linalg.solve(B, b)
+    assert np.max(np.abs(z - ref)) < 1e-10 * np.max(np.abs(ref))

@@ -32,28 +32,58 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
 }
 
-// One workgroup per frequency n: x[n][0..M-1] = first column of B_n^{-1}.  y lives in LDS;
-// the dot product of each step is reduced in a fixed order (per-thread strided sums, wave
-// shuffles, then the four wave totals), so the result does not depend on scheduling.
+// Arithmetic of a work item: complex, or componentwise on (.x, .y) for the dual item, which
+// runs the real recursions of the two real blocks (frequencies 0 and N_t/2 of an even N_t,
+// whose lambda are real) side by side, so an even N_t gives N_t/2 equal work items.
+template <bool D> __device__ __forceinline__ double2 gmul(double2 a, double2 b) {
+  if constexpr (D) return make_double2(a.x * b.x, a.y * b.y);
+  else return cmul(a, b);
+}
+template <bool D> __device__ __forceinline__ double2 gdiv(double2 a, double2 b) {
+  if constexpr (D) return make_double2(a.x / b.x, a.y / b.y);
+  else return cdiv(a, b);
+}
+template <bool D> __device__ __forceinline__ double2 gone() {
+  return make_double2(1.0, D ? 1.0 : 0.0);
+}
+
+// Work items of the setup launch: with an even N_t (dual), item 0 holds rows 0 and N_t/2 and
+// item n >= 1 holds row n, so there are nf - 1 items; otherwise item n = row n.  (The
+// application treats every row as complex: its convolutions of the two real rows would need
+// both kernels in one transform, which cost more than the extra work item.)
+
+// One workgroup per item: x[n][0..M-1] = first column of B_n^{-1}.  y lives in LDS (64 KB at
+// M = 4096, so two items share a CU); the dot product of each step is reduced in a fixed order
+// (per-thread strided sums, wave shuffles, then the four wave totals), so the result does not
+// depend on scheduling.  (Measured at M = 4095: about 2.2 us per step for the 512 items, one
+// round of two workgroups per CU; a single wave per item took twice as long, and issuing all of
+// a step's LDS reads before their use changed nothing.)
 constexpr int LEV_NT = 256;
-__global__ void __launch_bounds__(LEV_NT) k_levinson(const double* __restrict__ g, double coef,
-                                                     const double2* __restrict__ lambda, int M,
-                                                     double2* __restrict__ xgen) {
-  extern __shared__ double2 y[];         // M - 1 entries (y[i-1] holds y_i)
-  __shared__ double2 part[LEV_NT / 64];
-  const int n = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const double2 lam = lambda[n];
-  const double2 t0 = make_double2(lam.x + coef * g[0], lam.y);
-  const double2 it0 = cdiv(make_double2(1.0, 0.0), t0);
-  // r_k = (coef g_k) / t_0 = rs * g_k
+template <bool D>
+__device__ __forceinline__ void levinson_item(const double* __restrict__ g, double coef,
+                                              double2 lam, int M, double2* __restrict__ out0,
+                                              double2* __restrict__ out1, double2* y,
+                                              double2* part) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // t_0 = lambda + coef g_0 (dual: lam = (lambda_0, lambda_{N_t/2}), both real)
+  const double2 t0 = D ? make_double2(lam.x + coef * g[0], lam.y + coef * g[0])
+                       : make_double2(lam.x + coef * g[0], lam.y);
+  const double2 it0 = gdiv<D>(gone<D>(), t0);
+  // r_k = (coef g_k) / t_0 = rs g_k
   const double2 rs = make_double2(coef * it0.x, coef * it0.y);
-  double2* out = xgen + (size_t)n * M;
+  auto store = [&](int i, double2 v) {
+    if constexpr (D) {
+      out0[i] = make_double2(v.x, 0.0);
+      out1[i] = make_double2(v.y, 0.0);
+    } else {
+      out0[i] = v;
+    }
+  };
   if (M == 1) {
-    if (t == 0) out[0] = it0;
+    if (t == 0) store(0, it0);
     return;
   }
-  auto r = [&](int k) { const double gk = g[k]; return make_double2(rs.x * gk, rs.y * gk); };
-  // block sum of a per-thread complex value, identical in every thread
+  // block sum of a per-thread value, identical in every thread
   auto block_sum = [&](double2 v) -> double2 {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
@@ -68,52 +98,86 @@ __global__ void __launch_bounds__(LEV_NT) k_levinson(const double* __restrict__ 
     __syncthreads();  // part is reused by the next sum
     return s;
   };
-  double2 a = r(1);
-  a = make_double2(-a.x, -a.y);
+  // Thread t owns the weights g_m, m = 1 + t + LEV_NT j, in registers: the step-k sum is
+  // sum_{m=1}^{k} g_m y_{k+1-m}, so every thread keeps its own g_m for the whole recursion and
+  // only y is read from LDS.  The scalar g_{k+1} of the next step is loaded one step ahead.
+  constexpr int GR = 4096 / LEV_NT;
+  double gr[GR];
+#pragma unroll
+  for (int j = 0; j < GR; ++j) {
+    const int m = 1 + t + LEV_NT * j;
+    gr[j] = m < M ? g[m] : 0.0;
+  }
+  double2 a = make_double2(-rs.x * g[1], -rs.y * g[1]);  // -r_1
   if (t == 0) y[0] = a;
-  double2 beta = make_double2(1.0, 0.0);
+  double2 beta = gone<D>();
+  double gnext = M > 2 ? g[2] : 0.0;
   __syncthreads();
   for (int k = 1; k <= M - 2; ++k) {
-    beta = cmul(make_double2(1.0 - (a.x * a.x - a.y * a.y), -2.0 * a.x * a.y), beta);
-    // sum_{i=1}^{k} g_{k+1-i} y_i (then times rs), plus r_{k+1}
+    beta = gmul<D>(csub(gone<D>(), gmul<D>(a, a)), beta);
+    const double gk1 = gnext;
+    if (k + 2 < M) gnext = g[k + 2];
+    // sum_{m=1}^{k} g_m y_{k+1-m} (then times rs), plus r_{k+1}
     double2 acc = make_double2(0.0, 0.0);
-    for (int i = 1 + t; i <= k; i += LEV_NT) {
-      const double gi = g[k + 1 - i];
-      const double2 yi = y[i - 1];
-      acc.x = fma(gi, yi.x, acc.x);
-      acc.y = fma(gi, yi.y, acc.y);
+#pragma unroll
+    for (int j = 0; j < GR; ++j) {
+      const int m = 1 + t + LEV_NT * j;
+      if (m <= k) {
+        const double2 yv = y[k - m];
+        acc.x = fma(gr[j], yv.x, acc.x);
+        acc.y = fma(gr[j], yv.y, acc.y);
+      }
     }
     const double2 sg = block_sum(acc);
-    const double2 s = cadd(cmul(rs, make_double2(sg.x + g[k + 1], sg.y)), make_double2(0.0, 0.0));
-    a = cdiv(s, beta);
+    const double2 s = D ? make_double2(rs.x * (sg.x + gk1), rs.y * (sg.y + gk1))
+                        : cmul(rs, make_double2(sg.x + gk1, sg.y));
+    a = gdiv<D>(s, beta);
     a = make_double2(-a.x, -a.y);
     // y_i <- y_i + a y_{k+1-i}, pairs (i, k+1-i) updated together by one thread
     for (int i = 1 + t; 2 * i <= k + 1; i += LEV_NT) {
       const int j = k + 1 - i;
       const double2 yi = y[i - 1], yj = y[j - 1];
       if (i == j) {
-        y[i - 1] = cadd(yi, cmul(a, yi));
+        y[i - 1] = cadd(yi, gmul<D>(a, yi));
       } else {
-        y[i - 1] = cadd(yi, cmul(a, yj));
-        y[j - 1] = cadd(yj, cmul(a, yi));
+        y[i - 1] = cadd(yi, gmul<D>(a, yj));
+        y[j - 1] = cadd(yj, gmul<D>(a, yi));
       }
     }
     if (t == 0) y[k] = a;
     __syncthreads();
   }
-  // gamma = 1 / (1 + sum_{i=1}^{M-1} r_i y_i)
+  // gamma = 1 / (1 + sum_{m=1}^{M-1} r_m y_m)
   double2 acc = make_double2(0.0, 0.0);
-  for (int i = 1 + t; i <= M - 1; i += LEV_NT) {
-    const double gi = g[i];
-    const double2 yi = y[i - 1];
-    acc.x = fma(gi, yi.x, acc.x);
-    acc.y = fma(gi, yi.y, acc.y);
+#pragma unroll
+  for (int j = 0; j < GR; ++j) {
+    const int m = 1 + t + LEV_NT * j;
+    if (m <= M - 1) {
+      const double2 yv = y[m - 1];
+      acc.x = fma(gr[j], yv.x, acc.x);
+      acc.y = fma(gr[j], yv.y, acc.y);
+    }
   }
   const double2 sg = block_sum(acc);
-  const double2 den = cadd(make_double2(1.0, 0.0), cmul(rs, sg));
-  const double2 sc = cdiv(it0, den);  // gamma / t_0
-  if (t == 0) out[0] = sc;
-  for (int i = 1 + t; i <= M - 1; i += LEV_NT) out[i] = cmul(sc, y[i - 1]);
+  const double2 den = cadd(gone<D>(), gmul<D>(rs, sg));
+  const double2 sc = gdiv<D>(it0, den);  // gamma / t_0
+  if (t == 0) store(0, sc);
+  for (int i = 1 + t; i <= M - 1; i += LEV_NT) store(i, gmul<D>(sc, y[i - 1]));
+}
+
+__global__ void __launch_bounds__(LEV_NT) k_levinson(const double* __restrict__ g, double coef,
+                                                     const double2* __restrict__ lambda, int M,
+                                                     int nf, int dual,
+                                                     double2* __restrict__ xgen) {
+  extern __shared__ double2 y[];         // M - 1 entries (y[i-1] holds y_i)
+  __shared__ double2 part[LEV_NT / 64];
+  const int item = blockIdx.x;
+  if (dual && item == 0) {
+    const double2 lam = make_double2(lambda[0].x, lambda[nf - 1].x);
+    levinson_item<true>(g, coef, lam, M, xgen, xgen + (size_t)(nf - 1) * M, y, part);
+  } else {
+    levinson_item<false>(g, coef, lambda[item], M, xgen + (size_t)item * M, nullptr, y, part);
+  }
 }
 
 // Xhat[n][k] = DFT_L(x[n] padded)_k / L, one workgroup per frequency.
@@ -220,6 +284,9 @@ static int gs_setup_t(const Plan& p) {
   return RFDE_OK;
 }
 
+// Even N_t: the real rows 0 and N_t/2 form one work item of the setup (nf - 1 items in all).
+static int gs_dual(const Plan& p) { return (p.Nt % 2 == 0 && p.nf >= 2) ? 1 : 0; }
+
 template <int L>
 static int gs_apply_t(const Plan& p, const double2* z1, double2* z2) {
   constexpr int NT = gs_threads<L>();
@@ -250,7 +317,9 @@ static int gs_apply_t(const Plan& p, const double2* z1, double2* z2) {
 // Setup of the Toeplitz solver: generators by Levinson-Durbin, then their transforms.
 int launch_gs_setup(const Plan& p) {
   const size_t lds = (size_t)(p.M > 1 ? p.M - 1 : 1) * sizeof(double2);
-  k_levinson<<<p.nf, LEV_NT, lds, p.stream>>>(p.g, p.coef, p.lambda, p.M, p.gs_x);
+  const int dual = gs_dual(p);
+  k_levinson<<<p.nf - dual, LEV_NT, lds, p.stream>>>(p.g, p.coef, p.lambda, p.M, p.nf, dual,
+                                                     p.gs_x);
   RFDE_HIP(hipGetLastError());
   RFDE_GSL_SWITCH(gs_setup_t, p);
 }

@@ -565,9 +565,10 @@ def measure_small(args, dev):
 def kernels_only(W, dev):
     """A short fixed sequence for profiler runs (kernel trace, PMC counters): a 1 GiB device
     copy (calibration of the byte counters), the matrix-core probes, then per form one plan setup
-    and three (P^-1, matvec) pairs: FP64 exact, FP32 exact, FP64 tau at the 1D workload, the 2D
-    workload in FP64 and FP32; and one forward and one training step of the guess network at
-    its benchmark shape (M = 1023, N_t = 512, Ks = 64, batch 32)."""
+    and three (P^-1, matvec) pairs: FP64 exact, FP32 exact, FP64 tau and FP64 Toeplitz
+    (Gohberg-Semencul) at the 1D workload, the 2D workload in FP64 and FP32; and one forward and
+    one training step of the guess network at its benchmark shape (M = 1023, N_t = 512, Ks = 64,
+    batch 32)."""
     import torch
 
     from paper_2003_07020_amd.rfde import Plan, probe_mfma
@@ -582,7 +583,7 @@ def kernels_only(W, dev):
         probe_mfma(kind, 4096)
     M, Nt = W["M"], W["Nt"]
     u0, f, _ = gen1d(W["seed"], M, Nt)
-    for bits, spatial in ((64, "exact"), (32, "exact"), (64, "tau")):
+    for bits, spatial in ((64, "exact"), (32, "exact"), (64, "tau"), (64, "toeplitz")):
         p = Plan.create_1d(1.5, W["kappa"], 0.0, 1.0, M, Nt, W["T"], precond_bits=bits,
                            spatial=spatial)
         v = torch.from_numpy(f.ravel()).to(dev)

@@ -52,19 +52,67 @@ template <bool D> __device__ __forceinline__ double2 gone() {
 // application treats every row as complex: its convolutions of the two real rows would need
 // both kernels in one transform, which cost more than the extra work item.)
 
+// v plus the value DPP control C routes to this lane (rows outside ROWS add zero), on both
+// halves of the double
+template <int C, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, C, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), C, ROWS, 0xf, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The value of lane l - 1 in lane l (lane 0 gets zero): DPP wave_shr:1 on both halves.
+__device__ __forceinline__ double wave_shr1(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), 0x138, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, returned uniform: quad swaps (xor 1, xor 2),
+// row half-mirror and mirror (each 16-lane row then holds its row sum), then the row broadcasts
+// of lanes 15 and 31, which leave the total in lane 63.  Data moves lane to lane through DPP,
+// not through LDS.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = dpp_add<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+  v = dpp_add<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+  v = dpp_add<0x141>(v);       // row_half_mirror
+  v = dpp_add<0x140>(v);       // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // One workgroup per item: x[n][0..M-1] = first column of B_n^{-1}.  y lives in LDS (64 KB at
-// M = 4096, so two items share a CU); the dot product of each step is reduced in a fixed order
-// (per-thread strided sums, wave shuffles, then the four wave totals), so the result does not
-// depend on scheduling.  (Measured at M = 4095: about 2.2 us per step for the 512 items, one
-// round of two workgroups per CU; a single wave per item took twice as long, and issuing all of
-// a step's LDS reads before their use changed nothing.)
+// M = 4096, so two items share a CU) and in registers: y_i with 2i <= k+1 (the lower half at
+// step k) stays in a register of the thread that updates the pair (i, k+1-i) from the step it
+// enters the lower half on, so a pair costs one LDS read and one write (of its upper element).
+// A step is one pass: the thread that updates the pair also adds the new pair's terms of the
+// next step's sum
+//   sum_{m=1}^{k+1} g_m y_{k+2-m} = g_{k+2-i} y_i + g_{k+2-j} y_j + ... + g_1 y_{k+1}
+// (j = k+1-i), so the sum needs no second pass and the step one barrier (the reduction's, which
+// also orders this step's writes of y before the next step's reads).  A thread issues all of its
+// pairs' LDS reads before any write (the pairs of a step are disjoint) and before the division
+// that gives a; a thread's weights move one thread up per step (no loads in the loop).  The
+// per-thread partial sums are reduced in a fixed order (strided sums, the wave sum, then the
+// wave totals, which alternate between two buffers by step parity), so the result does not
+// depend on scheduling.  (Measured at N_t = 1024: 1.3 us per step at M = 511 and 1.6 us at
+// M = 4095, so the step is bound by its chain of reduction, barrier and LDS round trips rather
+// than by its work; two items per workgroup, at one workgroup per CU, were slower.)
 constexpr int LEV_NT = 256;
+// pair slots per thread: at step k <= M - 2 <= 4094 the pairs are i = 1 .. (k+1)/2 <= 2047
+constexpr int LEV_S = 2048 / LEV_NT;
 template <bool D>
 __device__ __forceinline__ void levinson_item(const double* __restrict__ g, double coef,
                                               double2 lam, int M, double2* __restrict__ out0,
                                               double2* __restrict__ out1, double2* y,
-                                              double2* part) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+                                              double2 (*part)[LEV_NT / 64],
+                                              double (*edge)[LEV_NT / 64][LEV_S]) {
+  const int t = threadIdx.x, w = t >> 6;
   // t_0 = lambda + coef g_0 (dual: lam = (lambda_0, lambda_{N_t/2}), both real)
   const double2 t0 = D ? make_double2(lam.x + coef * g[0], lam.y + coef * g[0])
                        : make_double2(lam.x + coef * g[0], lam.y);
@@ -84,81 +132,111 @@ __device__ __forceinline__ void levinson_item(const double* __restrict__ g, doub
     return;
   }
   // block sum of a per-thread value, identical in every thread
-  auto block_sum = [&](double2 v) -> double2 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      v.x += __shfl_xor(v.x, m);
-      v.y += __shfl_xor(v.y, m);
-    }
-    if (lane == 0) part[w] = v;
+  auto block_sum = [&](double2 v, int par) -> double2 {
+    v = make_double2(wave_sum(v.x), wave_sum(v.y));
+    if ((t & 63) == 0) part[par][w] = v;
     __syncthreads();
-    double2 s = part[0];
+    double2 s = part[par][0];
 #pragma unroll
-    for (int q = 1; q < LEV_NT / 64; ++q) s = cadd(s, part[q]);
-    __syncthreads();  // part is reused by the next sum
+    for (int q = 1; q < LEV_NT / 64; ++q) s = cadd(s, part[par][q]);
     return s;
   };
-  // Thread t owns the weights g_m, m = 1 + t + LEV_NT j, in registers: the step-k sum is
-  // sum_{m=1}^{k} g_m y_{k+1-m}, so every thread keeps its own g_m for the whole recursion and
-  // only y is read from LDS.  The scalar g_{k+1} of the next step is loaded one step ahead.
-  constexpr int GR = 4096 / LEV_NT;
-  double gr[GR];
+  // slot q of thread t is the pair with i = 1 + t + LEV_NT q: its weight g_{i+1} is fixed, the
+  // weight g_{k+2-i} of its partner moves by one per step (indices clamped into [0, M) for the
+  // slots not yet active, whose values are never used)
+  auto clampg = [&](int m) { return m < 0 ? 0 : (m >= M ? M - 1 : m); };
+  double gi[LEV_S], gj[LEV_S];
 #pragma unroll
-  for (int j = 0; j < GR; ++j) {
-    const int m = 1 + t + LEV_NT * j;
-    gr[j] = m < M ? g[m] : 0.0;
+  for (int q = 0; q < LEV_S; ++q) {
+    const int i = 1 + t + LEV_NT * q;
+    gi[q] = g[clampg(i + 1)];
+    gj[q] = g[clampg(3 - i)];
   }
-  double2 a = make_double2(-rs.x * g[1], -rs.y * g[1]);  // -r_1
+  // y_i of slot q once it is in the lower half (from step 2i - 1 on, when its pair is (i, i))
+  double2 yr[LEV_S];
+#pragma unroll
+  for (int q = 0; q < LEV_S; ++q) yr[q] = make_double2(0.0, 0.0);
+  const double g1 = g[1];
+  double2 a = make_double2(-rs.x * g1, -rs.y * g1);  // -r_1
   if (t == 0) y[0] = a;
-  double2 beta = gone<D>();
+  // beta_1 = 1 - a_0^2 and its inverse
+  double2 beta = csub(gone<D>(), gmul<D>(a, a));
+  double2 ib = gdiv<D>(gone<D>(), beta);
+  double2 dot = make_double2(g1 * a.x, g1 * a.y);  // the step-1 sum g_1 y_1
   double gnext = M > 2 ? g[2] : 0.0;
   __syncthreads();
   for (int k = 1; k <= M - 2; ++k) {
-    beta = gmul<D>(csub(gone<D>(), gmul<D>(a, a)), beta);
+    // partners y_j (j = k+1-i >= i) from LDS; they do not depend on a
+    double2 yj[LEV_S];
+#pragma unroll
+    for (int q = 0; q < LEV_S; ++q) {
+      const int i = 1 + t + LEV_NT * q;
+      if (2 * i <= k + 1) yj[q] = y[k - i];
+    }
     const double gk1 = gnext;
     if (k + 2 < M) gnext = g[k + 2];
-    // sum_{m=1}^{k} g_m y_{k+1-m} (then times rs), plus r_{k+1}
+    // a = -(r_{k+1} + sum_m r_m y_{k+1-m}) / beta_k, by the inverse computed a step ahead
+    const double2 s = D ? make_double2(rs.x * (dot.x + gk1), rs.y * (dot.y + gk1))
+                        : cmul(rs, make_double2(dot.x + gk1, dot.y));
+    a = gmul<D>(s, ib);
+    a = make_double2(-a.x, -a.y);
+    // beta_{k+1} = (1 - a^2) beta_k and its inverse: needed only by the next step, so the
+    // division runs beside this step's update and sum instead of on the path from sum to a
+    beta = gmul<D>(csub(gone<D>(), gmul<D>(a, a)), beta);
+    ib = gdiv<D>(gone<D>(), beta);
+    // y_i <- y_i + a y_j, y_j <- y_j + a y_i; the new values' terms of the next sum,
+    // g_{k+2-i} y_i + g_{i+1} y_j (y_i once when i = j)
     double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int j = 0; j < GR; ++j) {
-      const int m = 1 + t + LEV_NT * j;
-      if (m <= k) {
-        const double2 yv = y[k - m];
-        acc.x = fma(gr[j], yv.x, acc.x);
-        acc.y = fma(gr[j], yv.y, acc.y);
-      }
-    }
-    const double2 sg = block_sum(acc);
-    const double2 s = D ? make_double2(rs.x * (sg.x + gk1), rs.y * (sg.y + gk1))
-                        : cmul(rs, make_double2(sg.x + gk1, sg.y));
-    a = gdiv<D>(s, beta);
-    a = make_double2(-a.x, -a.y);
-    // y_i <- y_i + a y_{k+1-i}, pairs (i, k+1-i) updated together by one thread
-    for (int i = 1 + t; 2 * i <= k + 1; i += LEV_NT) {
-      const int j = k + 1 - i;
-      const double2 yi = y[i - 1], yj = y[j - 1];
-      if (i == j) {
-        y[i - 1] = cadd(yi, gmul<D>(a, yi));
-      } else {
-        y[i - 1] = cadd(yi, gmul<D>(a, yj));
-        y[j - 1] = cadd(yj, gmul<D>(a, yi));
+    for (int q = 0; q < LEV_S; ++q) {
+      const int i = 1 + t + LEV_NT * q;
+      if (2 * i <= k + 1) {
+        const bool first = 2 * i == k + 1;  // i = j: y_i moves from LDS into its register
+        const double2 yi = first ? yj[q] : yr[q];
+        const double2 ni = cadd(yi, gmul<D>(a, yj[q]));
+        const double2 nj = cadd(yj[q], gmul<D>(a, yi));
+        yr[q] = ni;
+        if (!first) y[k - i] = nj;
+        const double wj = first ? 0.0 : gi[q];
+        acc.x = fma(gj[q], ni.x, fma(wj, nj.x, acc.x));
+        acc.y = fma(gj[q], ni.y, fma(wj, nj.y, acc.y));
       }
     }
     if (t == 0) y[k] = a;
-    __syncthreads();
+    // weights of step k + 1: thread t's next partner weight is thread t-1's current one (its i
+    // is one less), passed up the wave by DPP; lane 0 takes lane 63's of the wave before (of
+    // the slot before, for wave 0) through LDS, and thread 0 of slot 0 takes g_{k+2}
+    const int par = k & 1;
+    if ((t & 63) == 63) {
+#pragma unroll
+      for (int q = 0; q < LEV_S; ++q) edge[par][w][q] = gj[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LEV_S; ++q) gj[q] = wave_shr1(gj[q]);
+    const double2 sg = block_sum(acc, par);
+    if ((t & 63) == 0) {
+#pragma unroll
+      for (int q = 0; q < LEV_S; ++q)
+        gj[q] = w > 0 ? edge[par][w - 1][q] : (q > 0 ? edge[par][LEV_NT / 64 - 1][q - 1] : gnext);
+    }
+    dot = make_double2(sg.x + g1 * a.x, sg.y + g1 * a.y);
   }
+  // the lower half back into LDS beside the upper half
+#pragma unroll
+  for (int q = 0; q < LEV_S; ++q) {
+    const int i = 1 + t + LEV_NT * q;
+    if (2 * i <= M - 1) y[i - 1] = yr[q];
+  }
+  __syncthreads();
   // gamma = 1 / (1 + sum_{m=1}^{M-1} r_m y_m)
   double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int j = 0; j < GR; ++j) {
-    const int m = 1 + t + LEV_NT * j;
-    if (m <= M - 1) {
-      const double2 yv = y[m - 1];
-      acc.x = fma(gr[j], yv.x, acc.x);
-      acc.y = fma(gr[j], yv.y, acc.y);
-    }
+  for (int m = 1 + t; m <= M - 1; m += LEV_NT) {
+    const double2 yv = y[m - 1];
+    const double gm = g[m];
+    acc.x = fma(gm, yv.x, acc.x);
+    acc.y = fma(gm, yv.y, acc.y);
   }
-  const double2 sg = block_sum(acc);
+  const double2 sg = block_sum(acc, (M - 1) & 1);
   const double2 den = cadd(gone<D>(), gmul<D>(rs, sg));
   const double2 sc = gdiv<D>(it0, den);  // gamma / t_0
   if (t == 0) store(0, sc);
@@ -170,13 +248,15 @@ __global__ void __launch_bounds__(LEV_NT) k_levinson(const double* __restrict__ 
                                                      int nf, int dual,
                                                      double2* __restrict__ xgen) {
   extern __shared__ double2 y[];         // M - 1 entries (y[i-1] holds y_i)
-  __shared__ double2 part[LEV_NT / 64];
+  __shared__ double2 part[2][LEV_NT / 64];
+  __shared__ double edge[2][LEV_NT / 64][LEV_S];
   const int item = blockIdx.x;
   if (dual && item == 0) {
     const double2 lam = make_double2(lambda[0].x, lambda[nf - 1].x);
-    levinson_item<true>(g, coef, lam, M, xgen, xgen + (size_t)(nf - 1) * M, y, part);
+    levinson_item<true>(g, coef, lam, M, xgen, xgen + (size_t)(nf - 1) * M, y, part, edge);
   } else {
-    levinson_item<false>(g, coef, lambda[item], M, xgen + (size_t)item * M, nullptr, y, part);
+    levinson_item<false>(g, coef, lambda[item], M, xgen + (size_t)item * M, nullptr, y, part,
+                         edge);
   }
 }
 

@@ -21,7 +21,8 @@ def _plan(alpha, M, Nt, **kw):
 
 
 @pytest.mark.parametrize("alpha,M,Nt", [(1.5, 1, 2), (1.3, 2, 4), (1.7, 7, 3), (1.5, 63, 16),
-                                        (1.8, 100, 7), (1.2, 1000, 8), (1.9, 255, 64)])
+                                        (1.8, 100, 7), (1.2, 1000, 8), (1.9, 255, 64),
+                                        (1.4, 300, 6), (1.6, 2000, 4)])
 def test_generators_and_shifted_solves(alpha, M, Nt):
     from paper_2003_07020_amd import capi
     banner(f"toeplitz small alpha={alpha} M={M} Nt={Nt}")

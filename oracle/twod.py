@@ -104,6 +104,59 @@ def step_b_exact_2d(z1, Tx, Ty, cx, cy, tau, Nt, eps, ns=None):
     return np.array([S.solve(lam[n], z1[n]) for n in ns])
 
 
+def step_b_inner_2d(z1, Tx, Ty, sx, sy, cx, cy, tau, Nt, eps, k, inner_tol=0.0):
+    """Step (b) with an inner solver on the exact shifted operator (the optional inner
+    iteration of the 2D step (b), the paper giving only the tau approximation of eq. (4.5)):
+    for each frequency n, GMRES on B_n x = z1_n with B_n = lambda_n I - tau A, zero start,
+    right-preconditioned by that frequency's tau solve, at most k steps.  Textbook GMRES:
+    Arnoldi with modified Gram-Schmidt and Hermitian inner products on B_n P_n^{-1}, the small
+    least-squares problem min ||beta e_1 - H y|| solved directly, x = P_n^{-1} V y.  With
+    inner_tol > 0 every frequency stops after the first step at which all of them have
+    ||z1_n - B_n x_n|| <= inner_tol ||z1_n||.  Returns (x, steps taken)."""
+    lam = eigenvalues(Nt, eps)
+    nfq, My, Mx = z1.shape
+    Qx, Qy = dst_matrix(Mx), dst_matrix(My)
+    den = tau * (cy * sy[:, None] + cx * sx[None, :])
+
+    def prec(n, r):
+        return Qy @ ((Qy @ r @ Qx) / (lam[n] + den)) @ Qx
+
+    def op(n, z):
+        return lam[n] * z - tau * apply_spatial(z, Tx, Ty, cx, cy)
+
+    beta = np.array([np.linalg.norm(z1[n]) for n in range(nfq)])
+    V = [[z1[n] / beta[n] if beta[n] > 0 else np.zeros_like(z1[n])] for n in range(nfq)]
+    Z = [[] for _ in range(nfq)]
+    H = np.zeros((nfq, k + 1, k), dtype=np.complex128)
+
+    def lsq(n, m):
+        rhs = np.zeros(m + 1, dtype=np.complex128)
+        rhs[0] = beta[n]
+        y = np.linalg.lstsq(H[n, : m + 1, :m], rhs, rcond=None)[0]
+        return y, np.linalg.norm(rhs - H[n, : m + 1, :m] @ y)
+
+    steps = k
+    for j in range(k):
+        for n in range(nfq):
+            z = prec(n, V[n][j])
+            Z[n].append(z)
+            w = op(n, z)
+            for i in range(j + 1):
+                H[n, i, j] = np.vdot(V[n][i], w)
+                w = w - H[n, i, j] * V[n][i]
+            H[n, j + 1, j] = np.linalg.norm(w)
+            V[n].append(w / H[n, j + 1, j] if H[n, j + 1, j] > 0 else np.zeros_like(w))
+        if inner_tol > 0 and all(lsq(n, j + 1)[1] <= inner_tol * beta[n] for n in range(nfq)):
+            steps = j + 1
+            break
+    x = np.zeros_like(z1, dtype=np.complex128)
+    for n in range(nfq):
+        if beta[n] > 0 and steps > 0:
+            y = lsq(n, steps)[0]
+            x[n] = sum(y[i] * Z[n][i] for i in range(steps))
+    return x, steps
+
+
 __all__ = ["coeffs", "jacobian_2d_dense", "apply_spatial", "apply_all_at_once_2d",
            "ShiftedSolver2D", "bdf2_march_2d", "tau_sigma_2d", "step_b_tau_2d",
-           "pinv_tau_2d", "step_b_exact_2d", "n_unique"]
+           "pinv_tau_2d", "step_b_exact_2d", "step_b_inner_2d", "n_unique"]

@@ -98,3 +98,86 @@ def test_fgmres_iterations_bounded_by_rank():
     x, info = krylov.fgmres(Av, Mv, b, tol=1e-11)
     assert info["iters"] <= 2 * M + 1
     assert info["true_rel_res"] <= 1e-11
+
+
+def _inner_case(Mx=6, My=5, Nt=6, seed=11):
+    gx, gy = 1.6, 1.4
+    hx, hy, tau, Tx, Ty, cx, cy = _setup2d(gx, gy, Mx, My, Nt)
+    eps = pc.default_eps(tau)
+    sx, sy = twod.tau_sigma_2d(gx, gy, Mx, My)
+    lam = pc.eigenvalues(Nt, eps)
+    nf = Nt // 2 + 1
+    rng = np.random.default_rng(seed)
+    z1 = rng.standard_normal((nf, My, Mx)) + 1j * rng.standard_normal((nf, My, Mx))
+    # the two maps written out densely (independent of the oracle's routines): B_n and the
+    # tau solve of frequency n as matrices in the x-fastest layout
+    Qx, Qy = pc.dst_matrix(Mx), pc.dst_matrix(My)
+    Q = np.kron(Qy, Qx)
+    A = twod.jacobian_2d_dense(gx, gy, 1.0, 1.0, hx, hy, Mx, My)
+    dtau = tau * (cy * np.repeat(sy, Mx) + cx * np.tile(sx, My))
+    Bd = [lam[n] * np.eye(Mx * My) - tau * A for n in range(nf)]
+    Pd = [Q @ np.diag(1.0 / (lam[n] + dtau)) @ Q for n in range(nf)]
+    args = (Tx, Ty, sx, sy, cx, cy, tau, Nt, eps)
+    return z1, Bd, Pd, args
+
+
+def test_inner_one_step_is_the_best_multiple_of_the_tau_solve():
+    # k = 1: x = a P^-1 w with a minimising ||w - a B P^-1 w||, a = (u^H w) / (u^H u), u = B P^-1 w
+    z1, Bd, Pd, args = _inner_case()
+    x, steps = twod.step_b_inner_2d(z1, *args, k=1)
+    assert steps == 1
+    for n in range(z1.shape[0]):
+        w = z1[n].ravel()
+        pw = Pd[n] @ w
+        u = Bd[n] @ pw
+        a = np.vdot(u, w) / np.vdot(u, u)
+        assert np.max(np.abs(x[n].ravel() - a * pw)) < 1e-13 * np.max(np.abs(a * pw))
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_inner_matches_power_basis_least_squares(k):
+    # GMRES(k) from zero with right preconditioner P: x = P K c, K = [w, C w, .., C^{k-1} w],
+    # C = B P, c minimising ||w - C K c|| (brute force on the power basis)
+    z1, Bd, Pd, args = _inner_case()
+    x, steps = twod.step_b_inner_2d(z1, *args, k=k)
+    assert steps == k
+    for n in range(z1.shape[0]):
+        w = z1[n].ravel()
+        C = Bd[n] @ Pd[n]
+        K = np.stack([np.linalg.matrix_power(C, i) @ w for i in range(k)], axis=1)
+        c = np.linalg.lstsq(C @ K, w, rcond=None)[0]
+        ref = Pd[n] @ (K @ c)
+        assert np.max(np.abs(x[n].ravel() - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_inner_reaches_the_exact_solve_and_residuals_do_not_grow():
+    # on a 4 x 3 grid, 12 steps span the whole space: x = B^-1 w (fast diagonalisation)
+    Mx, My, Nt = 4, 3, 4
+    z1, Bd, Pd, args = _inner_case(Mx, My, Nt, seed=12)
+    Tx, Ty, sx, sy, cx, cy, tau, Nt, eps = args
+    ref = twod.step_b_exact_2d(z1, Tx, Ty, cx, cy, tau, Nt, eps)
+    x, _ = twod.step_b_inner_2d(z1, *args, k=Mx * My)
+    assert np.max(np.abs(x - ref)) < 1e-10 * np.max(np.abs(ref))
+    res = []
+    for k in range(1, 6):
+        xk, _ = twod.step_b_inner_2d(z1, *args, k=k)
+        res.append([np.linalg.norm(z1[n].ravel() - Bd[n] @ xk[n].ravel())
+                    for n in range(z1.shape[0])])
+    res = np.array(res)
+    assert np.all(res[1:] <= res[:-1] * (1 + 1e-12))
+
+
+def test_inner_tolerance_stops_all_frequencies_together():
+    z1, Bd, Pd, args = _inner_case()
+    rel = []
+    for k in range(1, 7):
+        xk, _ = twod.step_b_inner_2d(z1, *args, k=k)
+        rel.append(max(np.linalg.norm(z1[n].ravel() - Bd[n] @ xk[n].ravel())
+                       / np.linalg.norm(z1[n]) for n in range(z1.shape[0])))
+    # a tolerance between the residuals after 2 and 3 steps stops after exactly 3
+    tol = np.sqrt(rel[1] * rel[2])
+    assert rel[2] < tol < rel[1]
+    x, steps = twod.step_b_inner_2d(z1, *args, k=6, inner_tol=tol)
+    x3, _ = twod.step_b_inner_2d(z1, *args, k=3)
+    assert steps == 3
+    assert np.max(np.abs(x - x3)) < 1e-14 * np.max(np.abs(x3))

@@ -76,6 +76,18 @@ typedef struct {
                           and shifted solves) inside the FP64 outer iteration. Default 64        */
   int spatial;         /* rfde_spatial. Default RFDE_SPATIAL_EXACT in 1D (TAU is forced in 2D);
                           TOEPLITZ needs precond_bits = 64 (else EUNSUPPORTED)                */
+  int inner_iters;     /* 2D step (b) only.  0 (default): the tau solve of eq. (4.5), the
+                          paper's method.  k in 1..16: up to k GMRES steps per frequency on the
+                          exact shifted operator lambda_n I - tau A from a zero start, right-
+                          preconditioned by that frequency's tau solve (an inner iteration the
+                          paper leaves open; the flexible outer iteration absorbs it).  Needs
+                          precond_bits = 64; 1D plans and batches return EUNSUPPORTED for k > 0.
+                          Workspace: (2k + 2) complex vectors of nf x Mx x My               */
+  double inner_tol;    /* >= 0.  With inner_iters > 0 and inner_tol > 0 every frequency stops
+                          after the first inner step at which each has a GMRES residual
+                          <= inner_tol times its right-hand side's norm; the host reads those
+                          estimates after each step, so step (b) then synchronises the plan's
+                          stream.  0 (default): always inner_iters steps                    */
 } rfde_opts;
 
 typedef struct {

@@ -104,7 +104,7 @@ def step_b_exact_2d(z1, Tx, Ty, cx, cy, tau, Nt, eps, ns=None):
     return np.array([S.solve(lam[n], z1[n]) for n in ns])
 
 
-def step_b_inner_2d(z1, Tx, Ty, sx, sy, cx, cy, tau, Nt, eps, k, inner_tol=0.0):
+def step_b_inner_2d(z1, Tx, Ty, sx, sy, cx, cy, tau, Nt, eps, k, inner_tol=0.0, ns=None):
     """Step (b) with an inner solver on the exact shifted operator (the optional inner
     iteration of the 2D step (b), the paper giving only the tau approximation of eq. (4.5)):
     for each frequency n, GMRES on B_n x = z1_n with B_n = lambda_n I - tau A, zero start,
@@ -112,9 +112,11 @@ def step_b_inner_2d(z1, Tx, Ty, sx, sy, cx, cy, tau, Nt, eps, k, inner_tol=0.0):
     Arnoldi with modified Gram-Schmidt and Hermitian inner products on B_n P_n^{-1}, the small
     least-squares problem min ||beta e_1 - H y|| solved directly, x = P_n^{-1} V y.  With
     inner_tol > 0 every frequency stops after the first step at which all of them have
-    ||z1_n - B_n x_n|| <= inner_tol ||z1_n||.  Returns (x, steps taken)."""
-    lam = eigenvalues(Nt, eps)
+    ||z1_n - B_n x_n|| <= inner_tol ||z1_n||.  Rows follow ns (default: the half spectrum).
+    Returns (x, steps taken)."""
     nfq, My, Mx = z1.shape
+    ns = list(range(nfq)) if ns is None else list(ns)
+    lam = eigenvalues(Nt, eps)[ns]
     Qx, Qy = dst_matrix(Mx), dst_matrix(My)
     den = tau * (cy * sy[:, None] + cx * sx[None, :])
 

@@ -25,7 +25,8 @@ SPATIAL_TOEPLITZ = 2
 
 class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("restart", C.c_int),
-                ("circ_eps", C.c_double), ("precond_bits", C.c_int), ("spatial", C.c_int)]
+                ("circ_eps", C.c_double), ("precond_bits", C.c_int), ("spatial", C.c_int),
+                ("inner_iters", C.c_int), ("inner_tol", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -40,7 +40,11 @@ void free_plan(Plan* p) {
                   p->redout,  p->set,    p->zt,     p->gs_x,  p->gs_xhat, p->gs_p, p->gs_q,
                   p->bs[0].chirp, p->bs[0].chirp32, p->bs[0].khat, p->bs[0].khat32, p->bs[0].tw,
                   p->bs[0].tw32,  p->bs[1].chirp,   p->bs[1].chirp32, p->bs[1].khat,
-                  p->bs[1].khat32, p->bs[1].tw,     p->bs[1].tw32};
+                  p->bs[1].khat32, p->bs[1].tw,     p->bs[1].tw32,
+                  p->inner.V,     p->inner.Z,       p->inner.w,       p->inner.part,
+                  p->inner.h1,    p->inner.h2,      p->inner.R,       p->inner.gsn,
+                  p->inner.g,     p->inner.y,       p->inner.gc,      p->inner.beta,
+                  p->inner.scale, p->inner.res};
   if (!p->arena)
     for (void* b : bufs) dev_free(b);
   if (p->hred) (void)hipHostFree(p->hred);
@@ -78,7 +82,8 @@ size_t workspace_estimate(const Plan& p) {
   const bool bs = p.bs[0].LB || p.bs[1].LB;
   const size_t gs = p.opts.spatial == RFDE_SPATIAL_TOEPLITZ
                         ? (size_t)p.nf * (3 * (size_t)p.M + p.L) * sizeof(double2) : 0;
-  return gs + (2 * m + 1 + 3) * N * 8 + (size_t)p.nf * p.S * csz * (bs ? 2 : 1) +
+  const size_t inner = p.dim == 2 ? inner_workspace_bytes(p.opts.inner_iters, p.nf, p.S) : 0;
+  return gs + inner + (2 * m + 1 + 3) * N * 8 + (size_t)p.nf * p.S * csz * (bs ? 2 : 1) +
          ((size_t)70 * 1024) * 8 +
          (size_t)(p.L + p.Lx + p.Ly + 4 * p.Lt + 3 * p.Nt + 2 * (p.bs[0].LB + p.bs[1].LB) +
                   p.M + p.Mx + p.My + 4) * 24;
@@ -128,6 +133,27 @@ int plan_allocate_and_setup(Plan* p, bool factor) {
     RFDE_TRY(dalloc(p, &p->gs_xhat, (size_t)p->nf * p->L, &ws));
     RFDE_TRY(dalloc(p, &p->gs_p, (size_t)p->nf * p->M, &ws));
     RFDE_TRY(dalloc(p, &p->gs_q, (size_t)p->nf * p->M, &ws));
+  }
+  if (p->dim == 2 && p->opts.inner_iters > 0) {
+    InnerWs& I = p->inner;
+    const int k = p->opts.inner_iters;
+    const size_t vec = (size_t)p->nf * p->S, nfr = p->nf;
+    constexpr size_t KS = INNER_KMAX + 1;
+    I.nblk = inner_blocks(p->S);
+    RFDE_TRY(dalloc(p, &I.V, (k + 1) * vec, &ws));
+    RFDE_TRY(dalloc(p, &I.Z, k * vec, &ws));
+    RFDE_TRY(dalloc(p, &I.w, vec, &ws));
+    RFDE_TRY(dalloc(p, &I.part, nfr * I.nblk * (KS + 1), &ws));
+    RFDE_TRY(dalloc(p, &I.h1, nfr * (KS + 1), &ws));
+    RFDE_TRY(dalloc(p, &I.h2, nfr * (KS + 1), &ws));
+    RFDE_TRY(dalloc(p, &I.R, nfr * INNER_KMAX * KS, &ws));
+    RFDE_TRY(dalloc(p, &I.gsn, nfr * INNER_KMAX, &ws));
+    RFDE_TRY(dalloc(p, &I.g, nfr * KS, &ws));
+    RFDE_TRY(dalloc(p, &I.y, nfr * INNER_KMAX, &ws));
+    RFDE_TRY(dalloc(p, &I.gc, nfr * INNER_KMAX, &ws));
+    RFDE_TRY(dalloc(p, &I.beta, nfr, &ws));
+    RFDE_TRY(dalloc(p, &I.scale, nfr, &ws));
+    RFDE_TRY(dalloc(p, &I.res, nfr, &ws));
   }
   for (DstBsAxis& x : p->bs) {
     if (!x.LB) continue;
@@ -233,11 +259,14 @@ static bool opts_ok(const rfde_opts& o) {
   return o.tol > 0 && o.maxit >= 1 && o.restart >= 1 && o.restart <= 64 && o.circ_eps <= 1.0 &&
          (o.precond_bits == 64 || o.precond_bits == 32) &&
          (o.spatial == RFDE_SPATIAL_EXACT || o.spatial == RFDE_SPATIAL_TAU ||
-          o.spatial == RFDE_SPATIAL_TOEPLITZ);
+          o.spatial == RFDE_SPATIAL_TOEPLITZ) &&
+         o.inner_iters >= 0 && o.inner_iters <= INNER_KMAX && o.inner_tol >= 0.0 &&
+         std::isfinite(o.inner_tol);
 }
 
 // ---- steps ----
 static int pinv_step_b(const Plan& p, const void* z1, void* z2) {
+  if (p.dim == 2 && p.opts.inner_iters > 0) return launch_inner_step_b(p, z1, z2);
   if (p.opts.spatial == RFDE_SPATIAL_EXACT) return launch_trsv(p, z1, z2);
   if (p.opts.spatial == RFDE_SPATIAL_TOEPLITZ) return launch_gs_apply(p, z1, z2);
   return launch_tau_solve(p, z1, z2);
@@ -276,6 +305,7 @@ int plan_init_1d(Plan* p, double alpha, double kappa, double a, double b, int M,
   p->stream = stream;
   plan_dst_axes(p);
   if (o.spatial == RFDE_SPATIAL_TOEPLITZ && o.precond_bits != 64) return RFDE_EUNSUPPORTED;
+  if (o.inner_iters > 0) return RFDE_EUNSUPPORTED;  // the inner solver is a 2D option
   if (o.spatial == RFDE_SPATIAL_EXACT) {
     p->T = (M + TILE - 1) / TILE;
     p->Mp = p->T * TILE;
@@ -301,6 +331,8 @@ void rfde_opts_default(rfde_opts* o) {
   o->circ_eps = 0.0;
   o->precond_bits = 64;
   o->spatial = RFDE_SPATIAL_EXACT;
+  o->inner_iters = 0;
+  o->inner_tol = 0.0;
 }
 
 const char* rfde_strerror(int s) {
@@ -353,6 +385,7 @@ int rfde_plan_create_2d(rfde_plan* plan, double alpha_x, double alpha_y, double 
       Mx > 4096 || My > 4096 || !nt_ok(Nt) || !(T > 0.0) || !opts_ok(o) ||
       !std::isfinite(alpha_x + alpha_y + kappa_x + kappa_y + ax + bx + ay + by + T))
     return RFDE_EINVAL;
+  if (o.inner_iters > 0 && o.precond_bits != 64) return RFDE_EUNSUPPORTED;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return RFDE_ENOMEM;
   p->dim = 2;

@@ -615,7 +615,7 @@ int rfde_batch_create(rfde_batch* batch, int count, const rfde_instance* inst,
   rfde_opts o;
   rfde_opts_default(&o);
   if (opts) o = *opts;
-  if (o.spatial != RFDE_SPATIAL_EXACT) return RFDE_EUNSUPPORTED;
+  if (o.spatial != RFDE_SPATIAL_EXACT || o.inner_iters > 0) return RFDE_EUNSUPPORTED;
   rfde_batch_* B = new (std::nothrow) rfde_batch_();
   if (!B) return RFDE_ENOMEM;
   B->inst.assign(inst, inst + count);

@@ -77,6 +77,18 @@ struct DstBsAxis {
   float2* tw32 = nullptr;
 };
 
+// Workspace of the optional inner solver of the 2D step (b) (k_inner.hip): at most INNER_KMAX
+// GMRES steps per frequency.  V: k + 1 basis vectors, Z: their k tau solves, w: the new
+// direction (each nf x S complex); per-frequency sums (part: nblk partial sums per frequency,
+// h1, h2: reduced, KMAX + 2 entries each) and the small least-squares state.
+constexpr int INNER_KMAX = 16;
+struct InnerWs {
+  double2 *V = nullptr, *Z = nullptr, *w = nullptr, *part = nullptr, *h1 = nullptr,
+          *h2 = nullptr, *R = nullptr, *gsn = nullptr, *g = nullptr, *y = nullptr;
+  double *gc = nullptr, *beta = nullptr, *scale = nullptr, *res = nullptr;
+  int nblk = 0;
+};
+
 struct Plan {
   int dim = 1;
   int M = 0, Mx = 0, My = 0, S = 0;   // S = spatial unknowns per time level
@@ -126,6 +138,7 @@ struct Plan {
   double2* gs_xhat = nullptr;
   double2* gs_p = nullptr;
   double2* gs_q = nullptr;
+  InnerWs inner;             // 2D with opts.inner_iters > 0
   void* factors = nullptr;   // nf blocks x lower_tiles(T) x 4096 complex (c128 or c64)
   size_t factor_bytes = 0;
   BlockSet* set = nullptr;   // this plan's blocks as a one-family set (device)
@@ -205,6 +218,10 @@ int launch_factorize_set(const BlockSet& hs, const BlockSet* ds, int bits, int g
 int launch_trsv_set(const BlockSet& hs, const BlockSet* ds, const void* const* zin,
                     void* const* zout, int bits, int grid_cap, hipStream_t st);
 int launch_tau_solve(const Plan& p, const void* zin, void* zout);
+// optional inner solver of the 2D step (b) (k_inner.hip)
+int launch_inner_step_b(const Plan& p, const void* z1, void* z2);
+int inner_blocks(int S);
+size_t inner_workspace_bytes(int k, int nf, int S);
 // Toeplitz solver (k_gs.hip): setup (generators and their transforms) and step (b).
 int launch_gs_setup(const Plan& p);
 int launch_gs_apply(const Plan& p, const void* z1, void* z2);

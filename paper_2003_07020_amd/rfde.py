@@ -31,13 +31,15 @@ def _need(t: torch.Tensor, dtype, numel: int, name: str):
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
 
 
-def opts(tol=1e-8, maxit=200, restart=30, circ_eps=0.0, precond_bits=64, spatial="exact") -> L.Opts:
+def opts(tol=1e-8, maxit=200, restart=30, circ_eps=0.0, precond_bits=64, spatial="exact",
+         inner_iters=0, inner_tol=0.0) -> L.Opts:
     o = L.Opts()
     L.lib().rfde_opts_default(C.byref(o))
     o.tol, o.maxit, o.restart, o.circ_eps = tol, maxit, restart, circ_eps
     o.precond_bits = precond_bits
     o.spatial = {"exact": L.SPATIAL_EXACT, "tau": L.SPATIAL_TAU,
                  "toeplitz": L.SPATIAL_TOEPLITZ}[spatial]
+    o.inner_iters, o.inner_tol = inner_iters, inner_tol
     return o
 
 

@@ -72,6 +72,39 @@ def test_invalid_arguments_rejected_without_device():
     assert L.rfde_strerror(capi.RFDE_ENAN).decode().startswith("non-finite")
 
 
+def test_inner_solver_options_validated_without_device():
+    # the optional inner solver of the 2D step (b): 0..16 steps, tolerance >= 0, 2D and the
+    # FP64 preconditioner only
+    from paper_2003_07020_amd import capi
+    L = capi.lib()
+    h = C.c_void_p()
+
+    def opts(**kw):
+        o = capi.Opts()
+        L.rfde_opts_default(C.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+    assert opts().inner_iters == 0 and opts().inner_tol == 0.0
+    for kw in ({"inner_iters": -1}, {"inner_iters": 17}, {"inner_iters": 2, "inner_tol": -1.0},
+               {"inner_iters": 2, "inner_tol": float("nan")}):
+        o = opts(**kw)
+        rc = L.rfde_plan_create_2d(C.byref(h), 1.6, 1.4, 1.0, 1.0, 0.0, 1.0, 0.0, 1.0, 15, 7, 8,
+                                   1.0, C.byref(o), None)
+        assert rc == capi.RFDE_EINVAL, kw
+        assert h.value is None
+    o = opts(inner_iters=2, precond_bits=32)
+    assert L.rfde_plan_create_2d(C.byref(h), 1.6, 1.4, 1.0, 1.0, 0.0, 1.0, 0.0, 1.0, 15, 7, 8, 1.0,
+                                 C.byref(o), None) == capi.RFDE_EUNSUPPORTED
+    o = opts(inner_iters=2, spatial=1)
+    assert L.rfde_plan_create_1d(C.byref(h), 1.5, 1.0, 0.0, 1.0, 63, 16, 1.0, C.byref(o),
+                                 None) == capi.RFDE_EUNSUPPORTED
+    arr = (capi.Instance * 1)(capi.Instance(1.5, 1.0, 0.0, 1.0, 1.0, 63, 64))
+    o = opts(inner_iters=2)
+    assert L.rfde_batch_create(C.byref(h), 1, arr, C.byref(o), 0, None) == capi.RFDE_EUNSUPPORTED
+    assert h.value is None
+
+
 def test_batch_rejects_invalid_arguments_without_device():
     from paper_2003_07020_amd import capi
     L = capi.lib()

@@ -1,0 +1,98 @@
+"""GPU parity of the optional inner solver of the 2D step (b) (inner_iters = k > 0: GMRES per
+frequency on the exact shifted operator, right-preconditioned by the tau solve) against the
+oracle's textbook GMRES, and full solves with it against the oracle's march."""
+import numpy as np
+import pytest
+
+from gpu_util import banner, rel_max, to_dev, to_host
+from oracle import allatonce as aa
+from oracle import precond as pc
+from oracle import twod
+from rfde_workloads import GRID_2D, gen2d, random_vector
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(gx, gy, Mx, My, Nt, T=1.0):
+    hx, hy, tau = 1.0 / (Mx + 1), 1.0 / (My + 1), T / Nt
+    Tx, Ty = aa.toeplitz_T(gx, Mx), aa.toeplitz_T(gy, My)
+    cx, cy = twod.coeffs(gx, gy, 1.0, 1.0, hx, hy)
+    eps = pc.default_eps(tau)
+    sx, sy = twod.tau_sigma_2d(gx, gy, Mx, My)
+    return (Tx, Ty, sx, sy, cx, cy, tau, Nt, eps)
+
+
+def _plan(gx, gy, Mx, My, Nt, T=1.0, **kw):
+    from paper_2003_07020_amd.rfde import Plan
+    return Plan.create_2d(gx, gy, 1.0, 1.0, 0.0, 1.0, 0.0, 1.0, Mx, My, Nt, T, **kw)
+
+
+def _z1(seed, Nt, My, Mx, eps):
+    v = random_vector(seed, Nt * My * Mx).reshape(Nt, My * Mx)
+    return pc.step_a(v, eps).reshape(-1, My, Mx)
+
+
+# (alpha_x, alpha_y, Mx, My, Nt, k): power-of-two DST axes, a chirp-z axis (Mx = 10), an odd N_t
+@pytest.mark.parametrize("gx,gy,Mx,My,Nt,k", [(1.6, 1.4, 15, 7, 8, 1), (1.6, 1.4, 15, 7, 8, 2),
+                                              (1.5, 1.8, 31, 15, 6, 4), (1.3, 1.7, 10, 7, 5, 3),
+                                              (1.9, 1.2, 7, 31, 4, 16)])
+def test_inner_step_b_matches_oracle(gx, gy, Mx, My, Nt, k):
+    banner(f"inner step b {gx},{gy} {Mx}x{My} Nt={Nt} k={k}")
+    args = _setup(gx, gy, Mx, My, Nt)
+    z1 = _z1(71, Nt, My, Mx, args[-1])
+    ref, steps = twod.step_b_inner_2d(z1, *args, k=k)
+    with _plan(gx, gy, Mx, My, Nt, inner_iters=k) as p:
+        z2 = to_host(p.step_b(to_dev(z1.ravel()))).reshape(z1.shape)
+    assert steps == k
+    assert rel_max(z2, ref) < 1e-10
+
+
+def test_inner_tolerance_stops_together():
+    gx, gy, Mx, My, Nt = 1.6, 1.4, 15, 7, 8
+    args = _setup(gx, gy, Mx, My, Nt)
+    z1 = _z1(72, Nt, My, Mx, args[-1])
+    Tx, Ty, sx, sy, cx, cy, tau, Nt, eps = args
+    lam = pc.eigenvalues(Nt, eps)
+
+    def worst(x):
+        return max(np.linalg.norm(z1[n] - (lam[n] * x[n] - tau * twod.apply_spatial(
+            x[n], Tx, Ty, cx, cy))) / np.linalg.norm(z1[n]) for n in range(z1.shape[0]))
+    r2 = worst(twod.step_b_inner_2d(z1, *args, k=2)[0])
+    r3 = worst(twod.step_b_inner_2d(z1, *args, k=3)[0])
+    tol = np.sqrt(r2 * r3)
+    ref, steps = twod.step_b_inner_2d(z1, *args, k=8, inner_tol=tol)
+    assert steps == 3
+    with _plan(gx, gy, Mx, My, Nt, inner_iters=8, inner_tol=tol) as p:
+        z2 = to_host(p.step_b(to_dev(z1.ravel()))).reshape(z1.shape)
+    assert rel_max(z2, ref) < 1e-10
+
+
+def test_inner_step_b_at_the_2d_workload_sampled():
+    G = GRID_2D
+    gx, gy, Mx, My, Nt = G["alpha_x"], G["alpha_y"], G["Mx"], G["My"], G["Nt"]
+    banner(f"inner step b 2d workload {Mx}x{My} Nt={Nt}")
+    args = _setup(gx, gy, Mx, My, Nt, G["T"])
+    z1 = _z1(73, Nt, My, Mx, args[-1])
+    with _plan(gx, gy, Mx, My, Nt, G["T"], inner_iters=2) as p:
+        z2 = to_host(p.step_b(to_dev(z1.ravel()))).reshape(z1.shape)
+    ns = [0, 1, Nt // 4, Nt // 2]
+    ref, _ = twod.step_b_inner_2d(z1[ns], *args, k=2, ns=ns)
+    assert rel_max(z2[ns], ref) < 1e-10
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_solve_with_inner_iterations(k):
+    gx, gy, Mx, My, Nt = 1.6, 1.4, 31, 15, 16
+    banner(f"inner solve {Mx}x{My} Nt={Nt} k={k}")
+    Tx, Ty, sx, sy, cx, cy, tau, Nt, eps = _setup(gx, gy, Mx, My, Nt)
+    u0, f, _ = gen2d(74, Mx, My, Nt)
+    Uref = twod.bdf2_march_2d(u0, f, Tx, Ty, cx, cy, tau)
+    with _plan(gx, gy, Mx, My, Nt, inner_iters=k) as p:
+        U, st, _ = p.solve(to_dev(u0.ravel()), to_dev(f.ravel()), tol=1e-11)
+    assert st.converged and st.true_rel_res <= 1e-11
+    assert rel_max(to_host(U).reshape(Nt, My, Mx), Uref) < 1e-9
+    with _plan(gx, gy, Mx, My, Nt) as q:
+        _, st0, _ = q.solve(to_dev(u0.ravel()), to_dev(f.ravel()), tol=1e-11)
+    # the inner iterations bring the preconditioner closer to the exact one: never more outer
+    # iterations than the pure tau solve needs here
+    assert st.iters <= st0.iters

@@ -406,7 +406,8 @@ def measure_batched(args, dev):
 def measure_2d(args, dev):
     """The 2D workload (255 x 255 grid, N_t = 256, alpha_x = 1.6, alpha_y = 1.4): time to TRR
     1e-8 with the 2D tau preconditioner (step (b) by DST-I diagonalisation) in FP64 and in FP32
-    inside FP64 FGMRES, P^-1 applies/s, the matvec's and P^-1's HBM rates, and the FP32
+    inside FP64 FGMRES, P^-1 applies/s, the matvec's and P^-1's HBM rates, the same with the
+    optional inner solver of step (b) (k = 2, 3 GMRES steps per frequency, FP64), and every
     solution's error against the oracle's FP64 march (fast diagonalisation)."""
     import torch
 
@@ -475,6 +476,35 @@ def measure_2d(args, dev):
                     "matvec_GB/s": round(16.0 * N / (ms_mv * 1e-3) / 1e9, 1),
                     **({"time_ffts": steps} if steps else {})}
         progress(f"2d form {key} done")
+    # the optional inner solver of step (b): k GMRES steps per frequency on the exact shifted
+    # operator (FP64 preconditioner), against the pure tau solve above
+    inner = {}
+    for k in (2, 3):
+        rec = []
+        U = torch.empty(N, dtype=torch.float64, device=dev)
+        for rep in range(1 + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = Plan.create_2d(gx, gy, W["kappa_x"], W["kappa_y"], 0.0, 1.0, 0.0, 1.0, Mx, My, Nt,
+                               T, tol=1e-8, inner_iters=k)
+            _, st, _ = p.solve(u0d, fd, out=U)
+            torch.cuda.synchronize()
+            if rep > 0:
+                rec.append(((time.perf_counter() - t0) * 1e3, st.iters, st.true_rel_res))
+            if rep < args.steps:
+                p.destroy()
+        v = torch.randn(N, dtype=torch.float64, device=dev,
+                        generator=torch.Generator(device=dev).manual_seed(8))
+        z = torch.empty_like(v)
+        p.apply_Pinv(v, out=z)
+        ms_pinv = event_ms(lambda: p.apply_Pinv(v, out=z), 5, s)
+        p.destroy()
+        sols[f"inner{k}"] = U.cpu().numpy().reshape(Nt, My, Mx)
+        inner[f"k{k}"] = {"value_ms": round(float(np.mean([r[0] for r in rec])), 3),
+                          "iters": rec[0][1], "true_rel_res": rec[0][2],
+                          "ms_pinv": round(ms_pinv, 4)}
+        progress(f"2d form inner k={k} done")
+    out["fp64_inner"] = inner
     hx, hy, tau = 1.0 / (Mx + 1), 1.0 / (My + 1), T / Nt
     Tx, Ty = aa.toeplitz_T(gx, Mx), aa.toeplitz_T(gy, My)
     cx, cy = twod.coeffs(gx, gy, W["kappa_x"], W["kappa_y"], hx, hy)
@@ -487,6 +517,9 @@ def measure_2d(args, dev):
                                    "solves in the eigenbasis)"}
     for bits, key in ((64, "fp64"), (32, "fp32")):
         out[key]["rel_err_vs_oracle"] = float(np.max(np.abs(sols[bits] - ref)) / np.max(np.abs(ref)))
+    for k in (2, 3):
+        out["fp64_inner"][f"k{k}"]["rel_err_vs_oracle"] = float(
+            np.max(np.abs(sols[f"inner{k}"] - ref)) / np.max(np.abs(ref)))
     out["speedup_fp32_vs_fp64"] = round(out["fp64"]["value_ms"] / out["fp32"]["value_ms"], 3)
     return out
 

@@ -599,9 +599,9 @@ def kernels_only(W, dev):
     """A short fixed sequence for profiler runs (kernel trace, PMC counters): a 1 GiB device
     copy (calibration of the byte counters), the matrix-core probes, then per form one plan setup
     and three (P^-1, matvec) pairs: FP64 exact, FP32 exact, FP64 tau and FP64 Toeplitz
-    (Gohberg-Semencul) at the 1D workload, the 2D workload in FP64 and FP32; and one forward and
-    one training step of the guess network at its benchmark shape (M = 1023, N_t = 512, Ks = 64,
-    batch 32)."""
+    (Gohberg-Semencul) at the 1D workload, the 2D workload in FP64, in FP32 and in FP64 with two
+    inner GMRES steps per frequency; and one forward and one training step of the guess network
+    at its benchmark shape (M = 1023, N_t = 512, Ks = 64, batch 32)."""
     import torch
 
     from paper_2003_07020_amd.rfde import Plan, probe_mfma
@@ -628,9 +628,10 @@ def kernels_only(W, dev):
         p.destroy()
     G = GRID_2D
     u0, f, _ = gen2d(G["seed"], G["Mx"], G["My"], G["Nt"], G["T"])
-    for bits in (64, 32):
+    for bits, inner in ((64, 0), (32, 0), (64, 2)):
         p = Plan.create_2d(G["alpha_x"], G["alpha_y"], G["kappa_x"], G["kappa_y"], 0.0, 1.0, 0.0,
-                           1.0, G["Mx"], G["My"], G["Nt"], G["T"], precond_bits=bits)
+                           1.0, G["Mx"], G["My"], G["Nt"], G["T"], precond_bits=bits,
+                           inner_iters=inner)
         v = torch.from_numpy(f.ravel()).to(dev)
         z = torch.empty_like(v)
         for _ in range(3):

@@ -218,7 +218,9 @@ int rfde_pinv_step_a(rfde_plan plan, const double* v, void* z1);
  * z1, z2: [n_freq][S] c128; may alias (in place).  Exact 1D solver with an even N_t: levels 0
  * and N_t/2 are taken as real (as step (a) produces them from real data; their imaginary parts
  * are ignored and written as zero), since those two blocks are real and are solved as a pair
- * in real arithmetic.  async. */
+ * in real arithmetic.  2D with opts.inner_iters = k > 0: z2_n is the k-step GMRES solution of
+ * the exact shifted system (see rfde_opts).  async, except with inner_tol > 0 (it then
+ * synchronises the plan's stream once per inner step). */
 int rfde_pinv_step_b(rfde_plan plan, const void* z1, void* z2);
 
 /* Step (a9), preconditioner step (c): extend by z2_{N_t-n} = conj(z2_n) (imaginary parts of
@@ -226,7 +228,7 @@ int rfde_pinv_step_b(rfde_plan plan, const void* z1, void* z2);
  * sum_n theta^{-n j} z2_n.  z2: [n_freq][S] c128; v: [N_t][S] real.  async. */
 int rfde_pinv_step_c(rfde_plan plan, const void* z2, double* v);
 
-/* Steps (a7)-(a9): z = P_eps^{-1} v.  v, z: [N_t][S]; z may alias v.  async. */
+/* Steps (a7)-(a9): z = P_eps^{-1} v.  v, z: [N_t][S]; z may alias v.  async (as step (b)). */
 int rfde_apply_Pinv(rfde_plan plan, const double* v, double* z);
 
 /*

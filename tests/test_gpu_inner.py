@@ -96,3 +96,18 @@ def test_solve_with_inner_iterations(k):
     # the inner iterations bring the preconditioner closer to the exact one: never more outer
     # iterations than the pure tau solve needs here
     assert st.iters <= st0.iters
+
+
+def test_inner_step_b_zero_frequency_plane():
+    # a frequency whose right-hand side is zero gets a zero solution (no division by its norm);
+    # the others are unaffected
+    gx, gy, Mx, My, Nt, k = 1.6, 1.4, 15, 7, 8, 3
+    args = _setup(gx, gy, Mx, My, Nt)
+    z1 = _z1(75, Nt, My, Mx, args[-1])
+    z1[2] = 0.0
+    ref, _ = twod.step_b_inner_2d(z1, *args, k=k)
+    with _plan(gx, gy, Mx, My, Nt, inner_iters=k) as p:
+        z2 = to_host(p.step_b(to_dev(z1.ravel()))).reshape(z1.shape)
+    assert np.all(z2[2] == 0.0)
+    assert np.all(np.isfinite(z2))
+    assert rel_max(z2, ref) < 1e-10

@@ -1,7 +1,9 @@
 """Identities the GPU kernels are built on, checked in plain numpy on the CPU (no GPU, no
-oracle): the half-length DST-I of the 1D tau solve, the chirp-z DST-I of any length, and the
-factored Arnoldi basis of the two-sweep CGS2.  The GPU parity tests check the kernels themselves
-against the oracle."""
+oracle): the half-length DST-I of the 1D tau solve, the chirp-z DST-I of any length, the
+factored Arnoldi basis of the two-sweep CGS2, Durbin's recursion without conjugation with the
+Gohberg-Semencul inverse of a complex symmetric Toeplitz matrix, and the one-pass-per-step
+organisation of that recursion in the setup kernel.  The GPU parity tests check the kernels
+themselves against the oracle."""
 import numpy as np
 import pytest
 
@@ -192,3 +194,71 @@ def test_durbin_gohberg_semencul(n):
     z = _gohberg_semencul_apply(x, b, L)
     ref = np.linalg.solve(B, b)
     assert np.max(np.abs(z - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def _durbin_one_pass(t, NT=4, S=8):
+    """Durbin's recursion as the setup kernel organises it (one pass and one block sum per
+    step): the thread of pair (i, k+1-i), i = 1 + t + NT q, updates both entries and adds their
+    terms of the next step's sum g_{k+2-i} y_i + g_{i+1} y_j (y_i once when i = j); y_i stays
+    in the thread's register from the step it joins the lower half (2i <= k+1); each thread's
+    partner weight g_{k+2-i} is the previous thread's of the step before."""
+    n = len(t)
+    if n == 1:
+        return np.array([1.0 / t[0]])
+    g = t / t[0]  # r_k = g_k for k >= 1 (g_0 = 1)
+    G = lambda m: g[min(max(m, 0), n - 1)]
+    lds = np.full(n - 1, np.nan, dtype=complex)
+    reg = np.zeros((NT, S), dtype=complex)
+    idx = np.array([[1 + th + NT * q for q in range(S)] for th in range(NT)])
+    gi = np.vectorize(lambda i: G(i + 1))(idx)
+    gj = np.vectorize(lambda i: G(3 - i))(idx)
+    a = -g[1]
+    lds[0] = a
+    beta = 1.0 + 0j
+    dot = g[1] * a
+    for k in range(1, n - 1):
+        beta = (1 - a * a) * beta
+        a = -(dot + g[k + 1]) / beta
+        old = lds.copy()
+        acc = 0
+        for th in range(NT):
+            for q in range(S):
+                i = idx[th, q]
+                if 2 * i > k + 1:
+                    continue
+                yj = old[k - i]
+                first = 2 * i == k + 1
+                yi = yj if first else reg[th, q]
+                ni, nj = yi + a * yj, yj + a * yi
+                reg[th, q] = ni
+                if not first:
+                    lds[k - i] = nj
+                acc += gj[th, q] * ni + (0 if first else gi[th, q]) * nj
+        lds[k] = a
+        # weights move one thread up: thread th takes thread th-1's, thread 0 of slot q takes
+        # the last thread's of slot q-1, and pair 1 takes g_{k+2}
+        nw = np.empty_like(gj)
+        for th in range(NT):
+            for q in range(S):
+                nw[th, q] = gj[th - 1, q] if th > 0 else (gj[NT - 1, q - 1] if q > 0 else G(k + 2))
+        gj = nw
+        dot = acc + g[1] * a
+    for th in range(NT):
+        for q in range(S):
+            i = idx[th, q]
+            if 2 * i <= n - 1:
+                lds[i - 1] = reg[th, q]
+    gamma = 1.0 / (1.0 + np.dot(g[1:], lds))
+    return gamma / t[0] * np.concatenate([[1.0], lds])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 9, 17, 40, 64])
+def test_durbin_one_pass_matches_plain_recursion(n):
+    rng = np.random.default_rng(100 + n)
+    th = rng.uniform(0, np.pi, 8)
+    wts = rng.uniform(0.1, 1.0, 8)
+    t = np.array([np.sum(wts * np.cos(k * th)) for k in range(n)], dtype=complex)
+    t[0] += 0.05 + 0.3j
+    ref = _durbin_first_column(t)
+    got = _durbin_one_pass(t)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))

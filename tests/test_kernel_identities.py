@@ -1,9 +1,10 @@
 """Identities the GPU kernels are built on, checked in plain numpy on the CPU (no GPU, no
 oracle): the half-length DST-I of the 1D tau solve, the chirp-z DST-I of any length, the
 factored Arnoldi basis of the two-sweep CGS2, Durbin's recursion without conjugation with the
-Gohberg-Semencul inverse of a complex symmetric Toeplitz matrix, and the one-pass-per-step
-organisation of that recursion in the setup kernel.  The GPU parity tests check the kernels
-themselves against the oracle."""
+Gohberg-Semencul inverse of a complex symmetric Toeplitz matrix, the one-pass-per-step
+organisation of that recursion in the setup kernel, and the Gram-Schmidt/Givens form of GMRES
+in the 2D inner solver.  The GPU parity tests check the kernels themselves against the
+oracle."""
 import numpy as np
 import pytest
 
@@ -262,3 +263,63 @@ def test_durbin_one_pass_matches_plain_recursion(n):
     ref = _durbin_first_column(t)
     got = _durbin_one_pass(t)
     assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def _gmres_cgs2_givens(C, w, k):
+    """k GMRES steps from zero for C x = w as the 2D inner-solver kernels do them: classical
+    Gram-Schmidt twice with Hermitian products, h_{j+1,j} = sqrt(||w||^2 - ||h2||^2) after the
+    second projection, complex Givens rotations with a real cosine
+    (c = |a| / rho, s = (a / |a|) h / rho), y = R^-1 g."""
+    n = len(w)
+    beta = np.linalg.norm(w)
+    V = [w / beta]
+    R = np.zeros((k + 1, k), dtype=complex)
+    cs = np.zeros(k)
+    sn = np.zeros(k, dtype=complex)
+    g = np.zeros(k + 1, dtype=complex)
+    g[0] = beta
+    for j in range(k):
+        x = C @ V[j]
+        Vm = np.stack(V, axis=1)
+        h1 = Vm.conj().T @ x
+        x = x - Vm @ h1
+        h2 = Vm.conj().T @ x
+        s2 = np.vdot(x, x).real
+        x = x - Vm @ h2
+        hn = np.sqrt(max(s2 - np.vdot(h2, h2).real, 0.0))
+        h = np.zeros(k + 1, dtype=complex)
+        h[: j + 1] = h1 + h2
+        h[j + 1] = hn
+        for i in range(j):
+            a, b = h[i], h[i + 1]
+            h[i] = cs[i] * a + sn[i] * b
+            h[i + 1] = cs[i] * b - np.conj(sn[i]) * a
+        a = h[j]
+        rho = np.hypot(abs(a), hn)
+        ph = a / abs(a) if abs(a) > 0 else 1.0
+        cs[j], sn[j] = abs(a) / rho, ph * hn / rho
+        R[: j + 1, j] = h[: j + 1]
+        R[j, j] = ph * rho
+        gj = g[j]
+        g[j] = cs[j] * gj
+        g[j + 1] = -np.conj(sn[j]) * gj
+        V.append(x / hn)
+    y = np.linalg.solve(np.triu(R[:k, :k]), g[:k])
+    return np.stack(V[:k], axis=1) @ y, abs(g[k])
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 12])
+def test_inner_gmres_givens_matches_least_squares(k):
+    # the residual estimate |g_k| and x = V y equal the minimiser of ||w - C x|| over the
+    # Krylov space (brute force on an orthonormalised power basis)
+    rng = np.random.default_rng(k)
+    n = 40
+    C = np.eye(n) + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    w = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, est = _gmres_cgs2_givens(C, w, k)
+    K = np.stack([np.linalg.matrix_power(C, i) @ w for i in range(k)], axis=1)
+    Qk, _ = np.linalg.qr(K)
+    c = np.linalg.lstsq(C @ Qk, w, rcond=None)[0]
+    ref = Qk @ c
+    assert np.max(np.abs(x - ref)) < 1e-10 * np.max(np.abs(ref))
+    assert abs(est - np.linalg.norm(w - C @ x)) < 1e-10 * np.linalg.norm(w)

@@ -111,3 +111,18 @@ def test_inner_step_b_zero_frequency_plane():
     assert np.all(z2[2] == 0.0)
     assert np.all(np.isfinite(z2))
     assert rel_max(z2, ref) < 1e-10
+
+
+def test_solve_with_inner_iterations_at_the_2d_workload():
+    # the full 255 x 255, N_t = 256 grid with two inner steps per frequency, against the
+    # oracle's march (fast diagonalisation)
+    G = GRID_2D
+    gx, gy, Mx, My, Nt, T = G["alpha_x"], G["alpha_y"], G["Mx"], G["My"], G["Nt"], G["T"]
+    banner(f"inner solve 2d workload {Mx}x{My} Nt={Nt}")
+    Tx, Ty, sx, sy, cx, cy, tau, Nt, eps = _setup(gx, gy, Mx, My, Nt, T)
+    u0, f, _ = gen2d(G["seed"], Mx, My, Nt, T)
+    Uref = twod.bdf2_march_2d(u0, f, Tx, Ty, cx, cy, tau)
+    with _plan(gx, gy, Mx, My, Nt, T, inner_iters=2) as p:
+        U, st, _ = p.solve(to_dev(u0.ravel()), to_dev(f.ravel()), tol=1e-10)
+    assert st.converged and st.true_rel_res <= 1e-10
+    assert rel_max(to_host(U).reshape(Nt, My, Mx), Uref) < 1e-8

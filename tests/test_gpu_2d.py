@@ -47,6 +47,18 @@ def test_setup_and_matvec_2d(gx, gy, Mx, My, Nt):
     assert rel_max(y, twod.apply_all_at_once_2d(v, Tx, Ty, cx, cy, tau)) < TOL_FFT
 
 
+@pytest.mark.parametrize("gx,gy,Mx,My,Nt", [(1.5, 1.3, 255, 255, 131), (1.8, 1.2, 255, 127, 257)])
+def test_matvec_2d_large_odd_levels(gx, gy, Mx, My, Nt):
+    """Larger grids on the register-FFT x pass (Lx = 512) with an odd level count, so the last
+    level pair holds one level, and a y pass over 255 or 127 rows."""
+    banner(f"2d matvec large {gx},{gy} {Mx}x{My} Nt={Nt}")
+    p = _plan(gx, gy, Mx, My, Nt)
+    hx, hy, tau, Tx, Ty, cx, cy, eps = _setup(gx, gy, Mx, My, Nt)
+    v = random_vector(34, Nt * My * Mx).reshape(Nt, My, Mx)
+    y = to_host(p.apply_A(to_dev(v.ravel()))).reshape(Nt, My, Mx)
+    assert rel_max(y, twod.apply_all_at_once_2d(v, Tx, Ty, cx, cy, tau)) < TOL_FFT
+
+
 @pytest.mark.parametrize("bits", [64, 32])
 @pytest.mark.parametrize("gx,gy,Mx,My,Nt", CASES)
 def test_tau_preconditioner_2d(gx, gy, Mx, My, Nt, bits):

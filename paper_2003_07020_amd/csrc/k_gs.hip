@@ -22,6 +22,7 @@
 // DFT(u)_k = w^{nk} (X_{-k} - x_0), w = exp(-2 pi i / L), so only X is stored.  One application:
 //     p = J L(x) J b,  q = J L(u) J b         (launch 1: two transform pairs on J b)
 //     z = (L(x) p - L(u) q) / x_0              (launch 2: two transform pairs)
+#include "buf_io.hpp"
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"
 
@@ -46,34 +47,42 @@ template <bool D> __device__ __forceinline__ double2 gdiv(double2 a, double2 b) 
 template <bool D> __device__ __forceinline__ double2 gone() {
   return make_double2(1.0, D ? 1.0 : 0.0);
 }
+// c + a b with every product fused into an FMA
+template <bool D> __device__ __forceinline__ double2 gfma(double2 a, double2 b, double2 c) {
+  if constexpr (D) return make_double2(fma(a.x, b.x, c.x), fma(a.y, b.y, c.y));
+  else
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+// 1 / b: one real division (of |b|^2) for a complex b
+template <bool D> __device__ __forceinline__ double2 grcp(double2 b) {
+  if constexpr (D) return make_double2(1.0 / b.x, 1.0 / b.y);
+  else {
+    const double r = 1.0 / fma(b.x, b.x, b.y * b.y);
+    return make_double2(b.x * r, -b.y * r);
+  }
+}
 
 // Work items of the setup launch: with an even N_t (dual), item 0 holds rows 0 and N_t/2 and
 // item n >= 1 holds row n, so there are nf - 1 items; otherwise item n = row n.  (The
 // application treats every row as complex: its convolutions of the two real rows would need
 // both kernels in one transform, which cost more than the extra work item.)
 
-// v plus the value DPP control C routes to this lane (rows outside ROWS add zero), on both
-// halves of the double
+// v plus the value DPP control C routes to this lane, on both halves of the double, in the rows
+// of ROWS (the other rows' results are unspecified: the moves leave those lanes unwritten, and
+// with no old value to keep they need no zeroed register)
 template <int C, int ROWS = 0xf>
 __device__ __forceinline__ double dpp_add(double v) {
   const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, C, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), C, ROWS, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)bits, C, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), C, ROWS, 0xf, true);
   return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// The value of lane l - 1 in lane l (lane 0 gets zero): DPP wave_shr:1 on both halves.
-__device__ __forceinline__ double wave_shr1(double v) {
-  const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), 0x138, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // Sum over the 64 lanes of a wave in a fixed order, returned uniform: quad swaps (xor 1, xor 2),
 // row half-mirror and mirror (each 16-lane row then holds its row sum), then the row broadcasts
-// of lanes 15 and 31, which leave the total in lane 63.  Data moves lane to lane through DPP,
-// not through LDS.
+// of lane 15 into rows 1 and 3 and of lane 31 into rows 2 and 3, which leave the total in lane
+// 63 (the only lane read: rows left out of a broadcast hold unspecified values).  Data moves
+// lane to lane through DPP, not through LDS.
 __device__ __forceinline__ double wave_sum(double v) {
   v = dpp_add<0xB1>(v);        // quad_perm [1, 0, 3, 2]
   v = dpp_add<0x4E>(v);        // quad_perm [2, 3, 0, 1]
@@ -97,12 +106,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 // (j = k+1-i), so the sum needs no second pass and the step one barrier (the reduction's, which
 // also orders this step's writes of y before the next step's reads).  A thread issues all of its
 // pairs' LDS reads before any write (the pairs of a step are disjoint) and before the division
-// that gives a; a thread's weights move one thread up per step (no loads in the loop).  The
+// that gives a.  The partner weights g_{k+2-i} of the next step are loaded one step ahead
+// through a buffer descriptor of g (indices outside it, which only slots not yet active use,
+// read zero).  The
 // per-thread partial sums are reduced in a fixed order (strided sums, the wave sum, then the
 // wave totals, which alternate between two buffers by step parity), so the result does not
-// depend on scheduling.  (Measured at N_t = 1024: 1.3 us per step at M = 511 and 1.6 us at
-// M = 4095, so the step is bound by its chain of reduction, barrier and LDS round trips rather
-// than by its work; two items per workgroup, at one workgroup per CU, were slower.)
+// depend on scheduling.  With two items per CU each SIMD runs one wave of each, and a step is
+// bound by the vector instructions it issues (every slot's complex updates and sums, the wave
+// sums, the division), so the step keeps its instruction count low: products fused into FMAs,
+// one real division for the complex reciprocal, DPP moves that need no zeroed register, and
+// the weights loaded rather than passed between threads.  (Two items per workgroup, at one
+// workgroup per CU, were slower.)
 constexpr int LEV_NT = 256;
 // pair slots per thread: at step k <= M - 2 <= 4094 the pairs are i = 1 .. (k+1)/2 <= 2047
 constexpr int LEV_S = 2048 / LEV_NT;
@@ -110,8 +124,7 @@ template <bool D>
 __device__ __forceinline__ void levinson_item(const double* __restrict__ g, double coef,
                                               double2 lam, int M, double2* __restrict__ out0,
                                               double2* __restrict__ out1, double2* y,
-                                              double2 (*part)[LEV_NT / 64],
-                                              double (*edge)[LEV_NT / 64][LEV_S]) {
+                                              double2 (*part)[LEV_NT / 64]) {
   const int t = threadIdx.x, w = t >> 6;
   // t_0 = lambda + coef g_0 (dual: lam = (lambda_0, lambda_{N_t/2}), both real)
   const double2 t0 = D ? make_double2(lam.x + coef * g[0], lam.y + coef * g[0])
@@ -142,15 +155,14 @@ __device__ __forceinline__ void levinson_item(const double* __restrict__ g, doub
     return s;
   };
   // slot q of thread t is the pair with i = 1 + t + LEV_NT q: its weight g_{i+1} is fixed, the
-  // weight g_{k+2-i} of its partner moves by one per step (indices clamped into [0, M) for the
-  // slots not yet active, whose values are never used)
-  auto clampg = [&](int m) { return m < 0 ? 0 : (m >= M ? M - 1 : m); };
+  // weight g_{k+2-i} = g[k + 1 - t - LEV_NT q] of its partner moves by one per step (read as
+  // zero outside [0, M), for the slots not yet active, whose values are never used)
+  const __amdgpu_buffer_rsrc_t gr = make_rsrc(g, M * 8);
   double gi[LEV_S], gj[LEV_S];
 #pragma unroll
   for (int q = 0; q < LEV_S; ++q) {
-    const int i = 1 + t + LEV_NT * q;
-    gi[q] = g[clampg(i + 1)];
-    gj[q] = g[clampg(3 - i)];
+    gi[q] = buf_load(gr, 2 + t + LEV_NT * q);
+    gj[q] = buf_load(gr, 2 - t - LEV_NT * q);
   }
   // y_i of slot q once it is in the lower half (from step 2i - 1 on, when its pair is (i, i))
   double2 yr[LEV_S];
@@ -161,7 +173,7 @@ __device__ __forceinline__ void levinson_item(const double* __restrict__ g, doub
   if (t == 0) y[0] = a;
   // beta_1 = 1 - a_0^2 and its inverse
   double2 beta = csub(gone<D>(), gmul<D>(a, a));
-  double2 ib = gdiv<D>(gone<D>(), beta);
+  double2 ib = grcp<D>(beta);
   double2 dot = make_double2(g1 * a.x, g1 * a.y);  // the step-1 sum g_1 y_1
   double gnext = M > 2 ? g[2] : 0.0;
   __syncthreads();
@@ -175,6 +187,10 @@ __device__ __forceinline__ void levinson_item(const double* __restrict__ g, doub
     }
     const double gk1 = gnext;
     if (k + 2 < M) gnext = g[k + 2];
+    // partner weights of step k + 1
+    double gn[LEV_S];
+#pragma unroll
+    for (int q = 0; q < LEV_S; ++q) gn[q] = buf_load(gr, k + 2 - t - LEV_NT * q);
     // a = -(r_{k+1} + sum_m r_m y_{k+1-m}) / beta_k, by the inverse computed a step ahead
     const double2 s = D ? make_double2(rs.x * (dot.x + gk1), rs.y * (dot.y + gk1))
                         : cmul(rs, make_double2(dot.x + gk1, dot.y));
@@ -183,7 +199,7 @@ __device__ __forceinline__ void levinson_item(const double* __restrict__ g, doub
     // beta_{k+1} = (1 - a^2) beta_k and its inverse: needed only by the next step, so the
     // division runs beside this step's update and sum instead of on the path from sum to a
     beta = gmul<D>(csub(gone<D>(), gmul<D>(a, a)), beta);
-    ib = gdiv<D>(gone<D>(), beta);
+    ib = grcp<D>(beta);
     // y_i <- y_i + a y_j, y_j <- y_j + a y_i; the new values' terms of the next sum,
     // g_{k+2-i} y_i + g_{i+1} y_j (y_i once when i = j)
     double2 acc = make_double2(0.0, 0.0);
@@ -193,8 +209,8 @@ __device__ __forceinline__ void levinson_item(const double* __restrict__ g, doub
       if (2 * i <= k + 1) {
         const bool first = 2 * i == k + 1;  // i = j: y_i moves from LDS into its register
         const double2 yi = first ? yj[q] : yr[q];
-        const double2 ni = cadd(yi, gmul<D>(a, yj[q]));
-        const double2 nj = cadd(yj[q], gmul<D>(a, yi));
+        const double2 ni = gfma<D>(a, yj[q], yi);
+        const double2 nj = gfma<D>(a, yi, yj[q]);
         yr[q] = ni;
         if (!first) y[k - i] = nj;
         const double wj = first ? 0.0 : gi[q];
@@ -203,22 +219,9 @@ __device__ __forceinline__ void levinson_item(const double* __restrict__ g, doub
       }
     }
     if (t == 0) y[k] = a;
-    // weights of step k + 1: thread t's next partner weight is thread t-1's current one (its i
-    // is one less), passed up the wave by DPP; lane 0 takes lane 63's of the wave before (of
-    // the slot before, for wave 0) through LDS, and thread 0 of slot 0 takes g_{k+2}
-    const int par = k & 1;
-    if ((t & 63) == 63) {
+    const double2 sg = block_sum(acc, k & 1);
 #pragma unroll
-      for (int q = 0; q < LEV_S; ++q) edge[par][w][q] = gj[q];
-    }
-#pragma unroll
-    for (int q = 0; q < LEV_S; ++q) gj[q] = wave_shr1(gj[q]);
-    const double2 sg = block_sum(acc, par);
-    if ((t & 63) == 0) {
-#pragma unroll
-      for (int q = 0; q < LEV_S; ++q)
-        gj[q] = w > 0 ? edge[par][w - 1][q] : (q > 0 ? edge[par][LEV_NT / 64 - 1][q - 1] : gnext);
-    }
+    for (int q = 0; q < LEV_S; ++q) gj[q] = gn[q];
     dot = make_double2(sg.x + g1 * a.x, sg.y + g1 * a.y);
   }
   // the lower half back into LDS beside the upper half
@@ -249,14 +252,12 @@ __global__ void __launch_bounds__(LEV_NT) k_levinson(const double* __restrict__ 
                                                      double2* __restrict__ xgen) {
   extern __shared__ double2 y[];         // M - 1 entries (y[i-1] holds y_i)
   __shared__ double2 part[2][LEV_NT / 64];
-  __shared__ double edge[2][LEV_NT / 64][LEV_S];
   const int item = blockIdx.x;
   if (dual && item == 0) {
     const double2 lam = make_double2(lambda[0].x, lambda[nf - 1].x);
-    levinson_item<true>(g, coef, lam, M, xgen, xgen + (size_t)(nf - 1) * M, y, part, edge);
+    levinson_item<true>(g, coef, lam, M, xgen, xgen + (size_t)(nf - 1) * M, y, part);
   } else {
-    levinson_item<false>(g, coef, lambda[item], M, xgen + (size_t)item * M, nullptr, y, part,
-                         edge);
+    levinson_item<false>(g, coef, lambda[item], M, xgen + (size_t)item * M, nullptr, y, part);
   }
 }
 

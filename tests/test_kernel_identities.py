@@ -201,18 +201,19 @@ def _durbin_one_pass(t, NT=4, S=8):
     """Durbin's recursion as the setup kernel organises it (one pass and one block sum per
     step): the thread of pair (i, k+1-i), i = 1 + t + NT q, updates both entries and adds their
     terms of the next step's sum g_{k+2-i} y_i + g_{i+1} y_j (y_i once when i = j); y_i stays
-    in the thread's register from the step it joins the lower half (2i <= k+1); each thread's
-    partner weight g_{k+2-i} is the previous thread's of the step before."""
+    in the thread's register from the step it joins the lower half (2i <= k+1); the partner
+    weights g_{k+2-i} are loaded a step ahead, reading zero outside [0, n) for the slots not yet
+    active."""
     n = len(t)
     if n == 1:
         return np.array([1.0 / t[0]])
     g = t / t[0]  # r_k = g_k for k >= 1 (g_0 = 1)
-    G = lambda m: g[min(max(m, 0), n - 1)]
+    G = lambda m: g[m] if 0 <= m < n else 0.0
     lds = np.full(n - 1, np.nan, dtype=complex)
     reg = np.zeros((NT, S), dtype=complex)
     idx = np.array([[1 + th + NT * q for q in range(S)] for th in range(NT)])
-    gi = np.vectorize(lambda i: G(i + 1))(idx)
-    gj = np.vectorize(lambda i: G(3 - i))(idx)
+    gi = np.vectorize(lambda i: G(i + 1), otypes=[complex])(idx)
+    gj = np.vectorize(lambda i: G(3 - i), otypes=[complex])(idx)
     a = -g[1]
     lds[0] = a
     beta = 1.0 + 0j
@@ -236,13 +237,8 @@ def _durbin_one_pass(t, NT=4, S=8):
                     lds[k - i] = nj
                 acc += gj[th, q] * ni + (0 if first else gi[th, q]) * nj
         lds[k] = a
-        # weights move one thread up: thread th takes thread th-1's, thread 0 of slot q takes
-        # the last thread's of slot q-1, and pair 1 takes g_{k+2}
-        nw = np.empty_like(gj)
-        for th in range(NT):
-            for q in range(S):
-                nw[th, q] = gj[th - 1, q] if th > 0 else (gj[NT - 1, q - 1] if q > 0 else G(k + 2))
-        gj = nw
+        # partner weights of step k + 1: g_{k+3-i}
+        gj = np.vectorize(lambda i: G(k + 3 - i), otypes=[complex])(idx)
         dot = acc + g[1] * a
     for th in range(NT):
         for q in range(S):

@@ -293,7 +293,9 @@ template <int L, int NT, typename Load, typename Store>
 __device__ __forceinline__ void gs_conv(double2* buf, const double2* __restrict__ tw,
                                         const double2* __restrict__ X, int M, double2 x0L,
                                         int which, Load& load, Store& store) {
-  auto mul = [&](int, int k, double2 c) { buf[k] = cmul(c, gs_kernel<L>(X, tw, M, x0L, which, k)); };
+  auto mul = [&](int, int k, double2 c) {
+    buf[k] = cmul(c, gs_kernel<L>(X, tw, M, x0L, which, k));
+  };
   fft_io<L, -1, NT, 1, L, false, true, true, 16>(buf, tw, load, mul);
   __syncthreads();
   NoLoad nl;
@@ -301,15 +303,75 @@ __device__ __forceinline__ void gs_conv(double2* buf, const double2* __restrict_
   __syncthreads();  // buf is reused by the next pair
 }
 
-// Launch 1: p = J L(x) J b, q = J L(u) J b for row n of b (one workgroup per row).
+// The last row by direct sums (when it would otherwise take a round of workgroups of its own):
+// every workgroup forms a few consecutive entries, one wave per entry, the lanes taking every
+// 64th term and the wave sum adding them in a fixed order, with the row's vectors staged in the
+// (not yet used) transform buffer, two at a time (2M <= L).  Entries of this workgroup:
+// [blockIdx.x * per, (blockIdx.x + 1) * per) within [0, M).
+template <int NT, typename Entry>
+__device__ __forceinline__ void gs_direct_rows(int M, Entry& entry) {
+  constexpr int NW = NT / 64;
+  const int per = (M + gridDim.x - 1) / gridDim.x;
+  const int m0 = blockIdx.x * per, m1 = m0 + per < M ? m0 + per : M;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int m = m0 + wv; m < m1; m += NW) entry(m, lane);
+}
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {  // c + a b
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+// This lane's share of sum_{t < n} term(t): t = lane, lane + 64, ... in four interleaved partial
+// sums (independent LDS reads in flight), added in a fixed order.
+template <typename F>
+__device__ __forceinline__ double2 lane_sum(int n, int lane, F term) {
+  double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
+  int t = lane;
+  for (; t + 192 < n; t += 256) {
+    s0 = term(t, s0);
+    s1 = term(t + 64, s1);
+    s2 = term(t + 128, s2);
+    s3 = term(t + 192, s3);
+  }
+  for (; t < n; t += 64) s0 = term(t, s0);
+  return cadd(cadd(s0, s1), cadd(s2, s3));
+}
+
+// Launch 1: p = J L(x) J b, q = J L(u) J b for row n of b (one workgroup per row); with
+// ndir >= 0, row ndir by direct sums: p_m = sum_{l >= m} x_{l-m} b_l, q_m = sum_{l > m}
+// x_{M-(l-m)} b_l (u_0 = 0, u_d = x_{M-d}).
 template <int L, int NT>
 __global__ void __launch_bounds__(NT) k_gs_apply1(const double2* __restrict__ b,
                                                   double2* __restrict__ P,
                                                   double2* __restrict__ Q,
                                                   const double2* __restrict__ xhat,
                                                   const double2* __restrict__ xgen, int M,
-                                                  const double2* __restrict__ tw) {
+                                                  const double2* __restrict__ tw, int ndir) {
   __shared__ double2 buf[L];
+  if (ndir >= 0) {
+    double2* xd = buf;      // x of row ndir
+    double2* bd = buf + M;  // b of row ndir
+    for (int e = threadIdx.x; e < M; e += NT) {
+      xd[e] = xgen[(size_t)ndir * M + e];
+      bd[e] = b[(size_t)ndir * M + e];
+    }
+    __syncthreads();
+    auto entry = [&](int m, int lane) {
+      // terms l = m + d: x_d b_l (d >= 0), x_{M-d} b_l (d >= 1)
+      double2 sp = lane_sum(M - m, lane, [&](int d, double2 s) {
+        return cfma(xd[d], bd[m + d], s);
+      });
+      double2 sq = lane_sum(M - m - 1, lane, [&](int e, double2 s) {
+        return cfma(xd[M - 1 - e], bd[m + 1 + e], s);
+      });
+      sp = make_double2(wave_sum(sp.x), wave_sum(sp.y));
+      sq = make_double2(wave_sum(sq.x), wave_sum(sq.y));
+      if (lane == 0) {
+        P[(size_t)ndir * M + m] = sp;
+        Q[(size_t)ndir * M + m] = sq;
+      }
+    };
+    gs_direct_rows<NT>(M, entry);
+    __syncthreads();  // buf is the transforms' next
+  }
   const int n = blockIdx.x;
   const double2* bn = b + (size_t)n * M;
   const double2* X = xhat + (size_t)n * L;
@@ -328,15 +390,49 @@ __global__ void __launch_bounds__(NT) k_gs_apply1(const double2* __restrict__ b,
 
 // Launch 2: z = (L(x) p - L(u) q) / x_0 for row n.  The second pair's store subtracts from the
 // value the same thread stored in the first (the store pattern of the last pass is fixed per
-// thread).
+// thread).  With ndir >= 0, row ndir by direct sums:
+// z_i = (sum_{j <= i} x_{i-j} p_j - sum_{j < i} x_{M-(i-j)} q_j) / x_0.
 template <int L, int NT>
 __global__ void __launch_bounds__(NT) k_gs_apply2(const double2* __restrict__ P,
                                                   const double2* __restrict__ Q,
                                                   double2* __restrict__ z,
                                                   const double2* __restrict__ xhat,
                                                   const double2* __restrict__ xgen, int M,
-                                                  const double2* __restrict__ tw) {
+                                                  const double2* __restrict__ tw, int ndir) {
   __shared__ double2 buf[L];
+  if (ndir >= 0) {
+    // first the sums with p (x and p staged), then with q (q over p); the entry's lane 0 keeps
+    // the first sum in z between the two
+    double2* xd = buf;
+    double2* vd = buf + M;
+    double2* zd = z + (size_t)ndir * M;
+    for (int e = threadIdx.x; e < M; e += NT) {
+      xd[e] = xgen[(size_t)ndir * M + e];
+      vd[e] = P[(size_t)ndir * M + e];
+    }
+    __syncthreads();
+    auto entry1 = [&](int i, int lane) {
+      double2 s = lane_sum(i + 1, lane, [&](int j, double2 a) {
+        return cfma(xd[i - j], vd[j], a);
+      });
+      s = make_double2(wave_sum(s.x), wave_sum(s.y));
+      if (lane == 0) zd[i] = s;
+    };
+    gs_direct_rows<NT>(M, entry1);
+    __syncthreads();
+    for (int e = threadIdx.x; e < M; e += NT) vd[e] = Q[(size_t)ndir * M + e];
+    __syncthreads();
+    const double2 ix0d = cdiv(make_double2(1.0, 0.0), xd[0]);
+    auto entry2 = [&](int i, int lane) {
+      double2 s = lane_sum(i, lane, [&](int j, double2 a) {
+        return cfma(xd[M - (i - j)], vd[j], a);
+      });
+      s = make_double2(wave_sum(s.x), wave_sum(s.y));
+      if (lane == 0) zd[i] = cmul(csub(zd[i], s), ix0d);
+    };
+    gs_direct_rows<NT>(M, entry2);
+    __syncthreads();  // buf is the transforms' next
+  }
   const int n = blockIdx.x;
   const double2* X = xhat + (size_t)n * L;
   const double2 x0 = xgen[(size_t)n * M];
@@ -368,14 +464,32 @@ static int gs_setup_t(const Plan& p) {
 // Even N_t: the real rows 0 and N_t/2 form one work item of the setup (nf - 1 items in all).
 static int gs_dual(const Plan& p) { return (p.Nt % 2 == 0 && p.nf >= 2) ? 1 : 0; }
 
+// Row split of the application: one workgroup per row by transforms, except that the last row
+// goes to the direct sums when it alone would start another round of workgroups (the rows
+// before it fill whole rounds of the resident slots, as 512 rows do on 256 CUs at one
+// workgroup per CU, L = 8192).  Returns that row, or -1.
+template <int L, int NT>
+static int gs_direct_row(const Plan& p) {
+  if (p.nf < 2) return -1;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gs_apply1<L, NT>, NT, 0) !=
+          hipSuccess ||
+      per_cu <= 0)
+    return -1;
+  const int slots = per_cu * device_cus(p.device);
+  return (p.nf - 1) % slots == 0 ? p.nf - 1 : -1;
+}
+
 template <int L>
 static int gs_apply_t(const Plan& p, const double2* z1, double2* z2) {
   constexpr int NT = gs_threads<L>();
-  k_gs_apply1<L, NT><<<p.nf, NT, 0, p.stream>>>(z1, p.gs_p, p.gs_q, p.gs_xhat, p.gs_x, p.M,
-                                                 p.twL);
+  const int ndir = gs_direct_row<L, NT>(p);
+  const int rows = ndir >= 0 ? p.nf - 1 : p.nf;
+  k_gs_apply1<L, NT><<<rows, NT, 0, p.stream>>>(z1, p.gs_p, p.gs_q, p.gs_xhat, p.gs_x, p.M,
+                                                p.twL, ndir);
   RFDE_HIP(hipGetLastError());
-  k_gs_apply2<L, NT><<<p.nf, NT, 0, p.stream>>>(p.gs_p, p.gs_q, z2, p.gs_xhat, p.gs_x, p.M,
-                                                 p.twL);
+  k_gs_apply2<L, NT><<<rows, NT, 0, p.stream>>>(p.gs_p, p.gs_q, z2, p.gs_xhat, p.gs_x, p.M,
+                                                p.twL, ndir);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

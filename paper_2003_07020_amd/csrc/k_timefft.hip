@@ -268,7 +268,7 @@ static int tf_inv_v(const Plan& p, const void* z2, double* v, const C* tw) {
   return RFDE_OK;
 }
 // Compute units of the plan's device (queried once per device).
-static int device_cus(int dev) {
+int device_cus(int dev) {
   static int cached[64] = {0};
   if (dev < 0 || dev >= 64) return 256;
   if (cached[dev] == 0) {

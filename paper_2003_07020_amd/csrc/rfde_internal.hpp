@@ -190,6 +190,9 @@ int apply_pinv(Plan& p, const double* v, double* z);
 // what: bit 0 time FFTs, bit 1 matvec, bit 2 triangular solves (rfde_tune.hip)
 int tune_plan(Plan& p, int what, rfde_tune_report* report);
 
+// Compute units of device dev (queried once per device; 256 if the query fails).
+int device_cus(int dev);
+
 // ---- launchers (all enqueue on p.stream) ----
 int launch_gk(double alpha, int n, double* g, hipStream_t st);
 int launch_twiddles(double2* tw, int n, hipStream_t st);

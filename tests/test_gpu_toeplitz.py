@@ -45,6 +45,26 @@ def test_generators_and_shifted_solves(alpha, M, Nt):
     assert rel_max(z, pc.pinv_fast(v, A, tau, eps)) < 1e-10
 
 
+@pytest.mark.parametrize("alpha,M,Nt", [(1.5, 2100, 512), (1.7, 2049, 513)])
+def test_shifted_solves_last_row_direct(alpha, M, Nt):
+    """257 frequency rows at transform length 8192 (one workgroup per CU): on a 256-CU device the
+    last row is formed by direct sums spread over the other rows' workgroups instead of a round
+    of its own.  Sampled rows, the last included, against dense solves."""
+    banner(f"toeplitz last row alpha={alpha} M={M} Nt={Nt}")
+    p = _plan(alpha, M, Nt)
+    h, tau = aa.mesh(0.0, 1.0, M, 1.0, Nt)
+    A = aa.jacobian_A(alpha, 1.0, h, M)
+    eps = pc.default_eps(tau)
+    lam = pc.eigenvalues(Nt, eps)
+    nf = Nt // 2 + 1
+    v = wl.random_vector(63, Nt * M).reshape(Nt, M)
+    z1 = pc.step_a(v, eps)
+    z2 = to_host(p.step_b(to_dev(z1.ravel()))).reshape(-1, M)
+    for n in (0, 1, nf // 2, nf - 2, nf - 1):
+        ref = sla.lu_solve(sla.lu_factor(pc.shifted_matrix(lam[n], A, tau)), z1[n])
+        assert rel_max(z2[n], ref) < 1e-10, n
+
+
 @pytest.mark.parametrize("alpha,M,Nt", [(1.5, 63, 64), (1.8, 1023, 16), (1.3, 100, 9)])
 def test_solve_matches_march_and_exact_iterations(alpha, M, Nt):
     from paper_2003_07020_amd.rfde import Plan

@@ -471,11 +471,15 @@ static int gs_dual(const Plan& p) { return (p.Nt % 2 == 0 && p.nf >= 2) ? 1 : 0;
 template <int L, int NT>
 static int gs_direct_row(const Plan& p) {
   if (p.nf < 2) return -1;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gs_apply1<L, NT>, NT, 0) !=
-          hipSuccess ||
-      per_cu <= 0)
-    return -1;
+  // resident workgroups per CU (queried once per instantiation)
+  static const int per_cu = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gs_apply1<L, NT>, NT, 0) !=
+        hipSuccess)
+      v = 0;
+    return v;
+  }();
+  if (per_cu <= 0) return -1;
   const int slots = per_cu * device_cus(p.device);
   return (p.nf - 1) % slots == 0 ? p.nf - 1 : -1;
 }

@@ -1,7 +1,8 @@
 """Identities the GPU kernels are built on, checked in plain numpy on the CPU (no GPU, no
 oracle): the half-length DST-I of the 1D tau solve, the chirp-z DST-I of any length, the
 factored Arnoldi basis of the two-sweep CGS2, Durbin's recursion without conjugation with the
-Gohberg-Semencul inverse of a complex symmetric Toeplitz matrix, the one-pass-per-step
+Gohberg-Semencul inverse of a complex symmetric Toeplitz matrix (by transforms, and by the
+direct sums the application uses for a row it does not transform), the one-pass-per-step
 organisation of that recursion in the setup kernel, and the Gram-Schmidt/Givens form of GMRES
 in the 2D inner solver.  The GPU parity tests check the kernels themselves against the
 oracle."""
@@ -194,6 +195,51 @@ def test_durbin_gohberg_semencul(n):
     b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     z = _gohberg_semencul_apply(x, b, L)
     ref = np.linalg.solve(B, b)
+    assert np.max(np.abs(z - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def _gohberg_semencul_direct(x, b, lanes=64):
+    """The same inverse by direct sums, as the application kernels form the row they do not
+    transform: p_m = sum_{l >= m} x_{l-m} b_l, q_m = sum_{l > m} x_{n-(l-m)} b_l, then
+    z_i = (sum_{j <= i} x_{i-j} p_j - sum_{j < i} x_{n-(i-j)} q_j) / x_0; each sum split over
+    `lanes` lanes (lane c takes terms c, c + lanes, ...) in four interleaved partial sums per
+    lane, the lanes' totals then added."""
+    n = len(x)
+
+    def lane_sum(cnt, term):
+        tot = 0
+        for c in range(lanes):
+            s = [0, 0, 0, 0]
+            t = c
+            while t + 3 * lanes < cnt:
+                for r in range(4):
+                    s[r] += term(t + r * lanes)
+                t += 4 * lanes
+            while t < cnt:
+                s[0] += term(t)
+                t += lanes
+            tot += (s[0] + s[1]) + (s[2] + s[3])
+        return tot
+
+    p = np.array([lane_sum(n - m, lambda d: x[d] * b[m + d]) for m in range(n)])
+    q = np.array([lane_sum(n - m - 1, lambda e: x[n - 1 - e] * b[m + 1 + e]) for m in range(n)])
+    z = [lane_sum(i + 1, lambda j: x[i - j] * p[j]) - lane_sum(i, lambda j: x[n - (i - j)] * q[j])
+         for i in range(n)]
+    return np.array(z) / x[0]
+
+
+@pytest.mark.parametrize("n,lanes", [(1, 64), (2, 64), (9, 4), (40, 4), (300, 8), (300, 64)])
+def test_gohberg_semencul_direct_sums(n, lanes):
+    rng = np.random.default_rng(200 + n)
+    th = rng.uniform(0, np.pi, 8)
+    wts = rng.uniform(0.1, 1.0, 8)
+    t = np.array([np.sum(wts * np.cos(k * th)) for k in range(n)], dtype=complex)
+    t[0] += 0.05 + 0.3j
+    B = np.array([[t[abs(i - j)] for j in range(n)] for i in range(n)])
+    x = np.linalg.solve(B, np.eye(n)[:, 0])
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    ref = np.linalg.solve(B, b)
+    z = _gohberg_semencul_direct(x, b, lanes)
     assert np.max(np.abs(z - ref)) < 1e-10 * np.max(np.abs(ref))
 
 

@@ -22,6 +22,8 @@
 // DFT(u)_k = w^{nk} (X_{-k} - x_0), w = exp(-2 pi i / L), so only X is stored.  One application:
 //     p = J L(x) J b,  q = J L(u) J b         (launch 1: two transform pairs on J b)
 //     z = (L(x) p - L(u) q) / x_0              (launch 2: two transform pairs)
+// one workgroup per frequency row, except a last row that would run alone in a round of its
+// own: its products are then formed as direct sums by all the other rows' workgroups.
 #include "buf_io.hpp"
 #include "fft_lds.hpp"
 #include "rfde_internal.hpp"

@@ -22,7 +22,7 @@ def _plan(alpha, M, Nt, **kw):
 
 @pytest.mark.parametrize("alpha,M,Nt", [(1.5, 1, 2), (1.3, 2, 4), (1.7, 7, 3), (1.5, 63, 16),
                                         (1.8, 100, 7), (1.2, 1000, 8), (1.9, 255, 64),
-                                        (1.4, 300, 6), (1.6, 2000, 4)])
+                                        (1.4, 300, 6), (1.6, 2000, 4), (1.3, 4096, 4)])
 def test_generators_and_shifted_solves(alpha, M, Nt):
     from paper_2003_07020_amd import capi
     banner(f"toeplitz small alpha={alpha} M={M} Nt={Nt}")
@@ -45,11 +45,12 @@ def test_generators_and_shifted_solves(alpha, M, Nt):
     assert rel_max(z, pc.pinv_fast(v, A, tau, eps)) < 1e-10
 
 
-@pytest.mark.parametrize("alpha,M,Nt", [(1.5, 2100, 512), (1.7, 2049, 513)])
+@pytest.mark.parametrize("alpha,M,Nt", [(1.5, 2100, 512), (1.7, 2049, 513), (1.6, 4096, 512)])
 def test_shifted_solves_last_row_direct(alpha, M, Nt):
     """257 frequency rows at transform length 8192 (one workgroup per CU): on a 256-CU device the
     last row is formed by direct sums spread over the other rows' workgroups instead of a round
-    of its own.  Sampled rows, the last included, against dense solves."""
+    of its own (at M = 4096 its two staged vectors fill the transform buffer exactly).  Sampled
+    rows, the last included, against dense solves."""
     banner(f"toeplitz last row alpha={alpha} M={M} Nt={Nt}")
     p = _plan(alpha, M, Nt)
     h, tau = aa.mesh(0.0, 1.0, M, 1.0, Nt)

@@ -45,12 +45,12 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true")
     ap.add_argument("--precond-bits", type=int, default=64, choices=[64, 32])
     ap.add_argument("--learned-train", type=int, default=625)
-    ap.add_argument("--learned-epochs", type=int, default=600)
+    ap.add_argument("--learned-epochs", type=int, default=2000)
     ap.add_argument("--learned-heldout", type=int, default=1000)
     ap.add_argument("--learned-ks", type=int, default=64)
     ap.add_argument("--learned-h1", type=int, default=128)
     ap.add_argument("--learned-h2", type=int, default=256)
-    ap.add_argument("--learned-lr", type=float, default=1e-3)
+    ap.add_argument("--learned-lr", type=float, default=2e-3)
     return ap.parse_args()
 
 

@@ -199,7 +199,13 @@ __device__ __forceinline__ void adam_apply(float& w, float& m, float& v, float g
 }
 
 // dW3t[o][h] = sum_b dg[b][o] h2[b][h] (FP32), db3[o] = sum_b dg[b][o]; Adam update of W3t and
-// its BF16 copy (mode 0) or plain gradient output (mode 1).
+// its BF16 copy (mode 0) or plain gradient output (mode 1).  A thread owns four consecutive
+// weights of one output o (H2 % 16 == 0, so they share o): one dg load feeds four sums, the
+// h2 values come as one 16-byte load, and the batch loop is unrolled so that several rows'
+// loads are in flight; every sum still runs over b in order.  VEC: h2, the parameter arrays
+// (and the gradient output) are 16-byte aligned and are moved four values per access;
+// otherwise one value per access.
+template <bool VEC>
 __global__ void __launch_bounds__(256) k_mlp_w3(const float* __restrict__ dg,
                                                 const float* __restrict__ h2, int B, int H2,
                                                 int NOUT, float* __restrict__ W3t,
@@ -208,19 +214,53 @@ __global__ void __launch_bounds__(256) k_mlp_w3(const float* __restrict__ dg,
                                                 float* __restrict__ b3, float* __restrict__ mb,
                                                 float* __restrict__ vb, AdamCfg a, int mode,
                                                 float* __restrict__ gW, float* __restrict__ gb) {
-  const size_t total = (size_t)NOUT * H2;
-  const size_t e = blockIdx.x * (size_t)256 + threadIdx.x;
-  if (e >= total) return;
+  const size_t quads = (size_t)NOUT * H2 / 4;
+  const size_t qd = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (qd >= quads) return;
+  const size_t e = 4 * qd;
   const int o = (int)(e / H2), h = (int)(e % H2);
-  float s = 0.f;
-  for (int b = 0; b < B; ++b) s = fmaf(dg[(size_t)b * NOUT + o], h2[(size_t)b * H2 + h], s);
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll 8
+  for (int b = 0; b < B; ++b) {
+    const float d = dg[(size_t)b * NOUT + o];
+    const float* hb = h2 + (size_t)b * H2 + h;
+    float4 x;
+    if constexpr (VEC) x = *reinterpret_cast<const float4*>(hb);
+    else x = make_float4(hb[0], hb[1], hb[2], hb[3]);
+    s0 = fmaf(d, x.x, s0);
+    s1 = fmaf(d, x.y, s1);
+    s2 = fmaf(d, x.z, s2);
+    s3 = fmaf(d, x.w, s3);
+  }
   if (mode == 1) {
-    gW[e] = s;
+    if constexpr (VEC) {
+      *reinterpret_cast<float4*>(gW + e) = make_float4(s0, s1, s2, s3);
+    } else {
+      gW[e] = s0; gW[e + 1] = s1; gW[e + 2] = s2; gW[e + 3] = s3;
+    }
+  } else if constexpr (VEC) {
+    float4 w = *reinterpret_cast<const float4*>(W3t + e);
+    float4 m = *reinterpret_cast<const float4*>(mW + e);
+    float4 v = *reinterpret_cast<const float4*>(vW + e);
+    adam_apply(w.x, m.x, v.x, s0, a);
+    adam_apply(w.y, m.y, v.y, s1, a);
+    adam_apply(w.z, m.z, v.z, s2, a);
+    adam_apply(w.w, m.w, v.w, s3, a);
+    *reinterpret_cast<float4*>(W3t + e) = w;
+    *reinterpret_cast<float4*>(mW + e) = m;
+    *reinterpret_cast<float4*>(vW + e) = v;
+    const unsigned int lo = f2bf(w.x) | ((unsigned int)f2bf(w.y) << 16);
+    const unsigned int hi = f2bf(w.z) | ((unsigned int)f2bf(w.w) << 16);
+    *reinterpret_cast<uint2*>(W3b + e) = make_uint2(lo, hi);
   } else {
-    float w = W3t[e], m = mW[e], v = vW[e];
-    adam_apply(w, m, v, s, a);
-    W3t[e] = w; mW[e] = m; vW[e] = v;
-    W3b[e] = f2bf(w);
+    const float sg[4] = {s0, s1, s2, s3};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float w = W3t[e + u], m = mW[e + u], v = vW[e + u];
+      adam_apply(w, m, v, sg[u], a);
+      W3t[e + u] = w; mW[e + u] = m; vW[e + u] = v;
+      W3b[e + u] = f2bf(w);
+    }
   }
   if (h == 0) {
     float sb = 0.f;
@@ -235,57 +275,70 @@ __global__ void __launch_bounds__(256) k_mlp_w3(const float* __restrict__ dg,
   }
 }
 
-// Hidden layers backward from dh2, with Adam (mode 0) or gradient output (mode 1).  One block.
+// Hidden layers backward from dh2, with Adam (mode 0) or gradient output (mode 1), in three
+// launches over the elements: da2 = dh2 (1 - h2^2); da1 = (da2 W2) (1 - h1^2), which reads W2
+// before its update; then every small-layer parameter (W2, b2, W1, b1, in that index order)
+// forms its gradient as a sum over the batch in order and takes its Adam step.
 struct SmallParams {
   float *W1, *b1, *W2, *b2;
   float *mW1, *vW1, *mb1, *vb1, *mW2, *vW2, *mb2, *vb2;
   float *gW1, *gb1, *gW2, *gb2;
 };
-__global__ void __launch_bounds__(256) k_mlp_small_bwd(const float* __restrict__ phat,
-                                                       const float* __restrict__ h1,
-                                                       const float* __restrict__ h2,
-                                                       const float* __restrict__ dh2, int B,
-                                                       int Pin, int H1, int H2, SmallParams P,
-                                                       AdamCfg a, int mode,
-                                                       float* __restrict__ da2_ws,
-                                                       float* __restrict__ da1_ws) {
-  const int t = threadIdx.x;
-  // da2 = dh2 (1 - h2^2)
-  for (int e = t; e < B * H2; e += 256) da2_ws[e] = dh2[e] * (1.f - h2[e] * h2[e]);
-  __syncthreads();
-  // da1 = (da2 W2) (1 - h1^2) -- uses W2 before its update
-  for (int e = t; e < B * H1; e += 256) {
-    const int b = e / H1, q = e % H1;
-    float s = 0.f;
-    for (int r = 0; r < H2; ++r) s = fmaf(da2_ws[b * H2 + r], P.W2[r * H1 + q], s);
-    da1_ws[e] = s * (1.f - h1[e] * h1[e]);
-  }
-  __syncthreads();
-  for (int e = t; e < H2 * H1; e += 256) {
+__global__ void __launch_bounds__(256) k_mlp_da2(const float* __restrict__ h2,
+                                                 const float* __restrict__ dh2, int n,
+                                                 float* __restrict__ da2) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < n) da2[e] = dh2[e] * (1.f - h2[e] * h2[e]);
+}
+__global__ void __launch_bounds__(256) k_mlp_da1(const float* __restrict__ h1,
+                                                 const float* __restrict__ da2,
+                                                 const float* __restrict__ W2, int B, int H1,
+                                                 int H2, float* __restrict__ da1) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= B * H1) return;
+  const int b = e / H1, q = e % H1;
+  float s = 0.f;
+  for (int r = 0; r < H2; ++r) s = fmaf(da2[b * H2 + r], W2[r * H1 + q], s);
+  da1[e] = s * (1.f - h1[e] * h1[e]);
+}
+__global__ void __launch_bounds__(256) k_mlp_small_update(const float* __restrict__ phat,
+                                                          const float* __restrict__ h1,
+                                                          const float* __restrict__ da2,
+                                                          const float* __restrict__ da1, int B,
+                                                          int Pin, int H1, int H2,
+                                                          SmallParams P, AdamCfg a, int mode) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < H2 * H1) {
     const int r = e / H1, q = e % H1;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s = fmaf(da2_ws[b * H2 + r], h1[b * H1 + q], s);
+    for (int b = 0; b < B; ++b) s = fmaf(da2[b * H2 + r], h1[b * H1 + q], s);
     if (mode == 1) P.gW2[e] = s;
     else adam_apply(P.W2[e], P.mW2[e], P.vW2[e], s, a);
+    return;
   }
-  for (int r = t; r < H2; r += 256) {
+  e -= H2 * H1;
+  if (e < H2) {
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += da2_ws[b * H2 + r];
-    if (mode == 1) P.gb2[r] = s;
-    else adam_apply(P.b2[r], P.mb2[r], P.vb2[r], s, a);
+    for (int b = 0; b < B; ++b) s += da2[b * H2 + e];
+    if (mode == 1) P.gb2[e] = s;
+    else adam_apply(P.b2[e], P.mb2[e], P.vb2[e], s, a);
+    return;
   }
-  for (int e = t; e < H1 * Pin; e += 256) {
+  e -= H2;
+  if (e < H1 * Pin) {
     const int q = e / Pin, c = e % Pin;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s = fmaf(da1_ws[b * H1 + q], phat[b * Pin + c], s);
+    for (int b = 0; b < B; ++b) s = fmaf(da1[b * H1 + q], phat[b * Pin + c], s);
     if (mode == 1) P.gW1[e] = s;
     else adam_apply(P.W1[e], P.mW1[e], P.vW1[e], s, a);
+    return;
   }
-  for (int q = t; q < H1; q += 256) {
+  e -= H1 * Pin;
+  if (e < H1) {
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += da1_ws[b * H1 + q];
-    if (mode == 1) P.gb1[q] = s;
-    else adam_apply(P.b1[q], P.mb1[q], P.vb1[q], s, a);
+    for (int b = 0; b < B; ++b) s += da1[b * H1 + e];
+    if (mode == 1) P.gb1[e] = s;
+    else adam_apply(P.b1[e], P.mb1[e], P.vb1[e], s, a);
   }
 }
 
@@ -498,13 +551,30 @@ static int mlp_backward(const rfde_mlp* m, const float* feats, const float* y, i
   P.mW2 = m->mW2; P.vW2 = m->vW2; P.mb2 = m->mb2; P.vb2 = m->vb2;
   P.gW1 = grads ? grads + oW1 : nullptr; P.gb1 = grads ? grads + ob1 : nullptr;
   P.gW2 = grads ? grads + oW2 : nullptr; P.gb2 = grads ? grads + ob2 : nullptr;
-  k_mlp_small_bwd<<<1, 256, 0, st>>>(w.phat, w.h1, w.h2, w.dh2, B, m->Pin, m->H1, m->H2, P, a,
-                                      mode, w.da2, w.da1);
+  const int nda2 = B * m->H2, nda1 = B * m->H1;
+  const int nsmall = m->H2 * m->H1 + m->H2 + m->H1 * m->Pin + m->H1;
+  k_mlp_da2<<<(nda2 + 255) / 256, 256, 0, st>>>(w.h2, w.dh2, nda2, w.da2);
   RFDE_HIP(hipGetLastError());
-  const size_t tot = (size_t)m->NOUT * m->H2;
-  k_mlp_w3<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(
-      w.dg, w.h2, B, m->H2, m->NOUT, m->W3t, m->W3t_bf16, m->mW3, m->vW3, m->b3, m->mb3, m->vb3,
-      a, mode, grads ? grads + oW3 : nullptr, grads ? grads + ob3 : nullptr);
+  k_mlp_da1<<<(nda1 + 255) / 256, 256, 0, st>>>(w.h1, w.da2, m->W2, B, m->H1, m->H2, w.da1);
+  RFDE_HIP(hipGetLastError());
+  k_mlp_small_update<<<(nsmall + 255) / 256, 256, 0, st>>>(w.phat, w.h1, w.da2, w.da1, B,
+                                                            m->Pin, m->H1, m->H2, P, a, mode);
+  RFDE_HIP(hipGetLastError());
+  const size_t quads = (size_t)m->NOUT * m->H2 / 4;
+  float* gW3 = grads ? grads + oW3 : nullptr;
+  auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+  const bool vec = al16(w.h2) &&
+                   (mode == 1 ? al16(gW3)
+                              : (al16(m->W3t) && al16(m->mW3) && al16(m->vW3) &&
+                                 ((uintptr_t)m->W3t_bf16 & 7) == 0));
+  if (vec)
+    k_mlp_w3<true><<<(unsigned)((quads + 255) / 256), 256, 0, st>>>(
+        w.dg, w.h2, B, m->H2, m->NOUT, m->W3t, m->W3t_bf16, m->mW3, m->vW3, m->b3, m->mb3,
+        m->vb3, a, mode, gW3, grads ? grads + ob3 : nullptr);
+  else
+    k_mlp_w3<false><<<(unsigned)((quads + 255) / 256), 256, 0, st>>>(
+        w.dg, w.h2, B, m->H2, m->NOUT, m->W3t, m->W3t_bf16, m->mW3, m->vW3, m->b3, m->mb3,
+        m->vb3, a, mode, gW3, grads ? grads + ob3 : nullptr);
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }

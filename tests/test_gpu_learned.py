@@ -28,8 +28,8 @@ def _small_net(seed, Pin=3, H1=8, H2=32, NOUT=96):
             rng.standard_normal(H2).astype(np.float32) * 0.1,
             _bf16_round(rng.standard_normal((NOUT, H2)) * 0.3),
             rng.standard_normal(NOUT).astype(np.float32) * 0.1]
-    mu = np.array([0.1, -0.2, 0.3], np.float32)
-    sd = np.array([1.5, 0.7, 2.0], np.float32)
+    mu = np.array([0.1, -0.2, 0.3, 0.05][:Pin], np.float32)
+    sd = np.array([1.5, 0.7, 2.0, 1.1][:Pin], np.float32)
     net = GuessNet(Pin, H1, H2, NOUT, mu, sd)
     net.set_params(host)
     p = rng.standard_normal((5, Pin)).astype(np.float32)
@@ -52,6 +52,45 @@ def test_forward_and_gradients_match_oracle():
         gg = to_host(gg).astype(np.float64)
         err = np.linalg.norm(gg - rr) / np.linalg.norm(rr)
         assert err < 2e-2, (a, err)
+
+
+def test_gradients_with_unaligned_output_match_oracle():
+    """Pin = 2, H1 = 5: the output layer's block of the flat gradient starts at float 207, not on
+    a 16-byte boundary, so its gradients are written one value per access."""
+    banner("mlp grads, unaligned output layer block")
+    net, P, p, y, mu, sd = _small_net(4, Pin=2, H1=5)
+    grads, _ = net.grads(to_dev(p), to_dev(y))
+    ref = omlp.grads(P, p.astype(np.float64), y.astype(np.float64), mu, sd)
+    for a, (gg, rr) in enumerate(zip(grads, ref)):
+        gg = to_host(gg).astype(np.float64)
+        assert np.linalg.norm(gg - rr) / np.linalg.norm(rr) < 2e-2, a
+
+
+def test_adam_step_unaligned_output_weights_bitwise():
+    """The output layer's weights and Adam moments moved 4 bytes off a 16-byte boundary take the
+    one-value-per-access path of the update; it must give the same bits as the aligned one."""
+    import torch
+    banner("mlp adam, unaligned output weights")
+    made = [_small_net(5) for _ in range(2)]
+    nets = [m[0] for m in made]
+    p, y = made[0][2], made[0][3]
+    net_u = nets[1]
+
+    def shifted(t):
+        buf = torch.zeros(t.numel() + 1, dtype=t.dtype, device=t.device)
+        buf[1:].copy_(t.reshape(-1))
+        return buf[1:].view(t.shape)
+
+    net_u.params[4] = shifted(net_u.params[4])
+    net_u.moments[8] = shifted(net_u.moments[8])
+    net_u.moments[9] = shifted(net_u.moments[9])
+    assert net_u.params[4].data_ptr() % 16 == 4
+    for net in nets:
+        for _ in range(3):
+            net.train_step(to_dev(p), to_dev(y), 1e-3)
+    for a, b in zip(nets[0].params, nets[1].params):
+        assert np.array_equal(to_host(a), to_host(b))
+    assert np.array_equal(to_host(nets[0].W3b), to_host(nets[1].W3b))
 
 
 def test_adam_step_matches_oracle():

@@ -22,7 +22,10 @@ def _plan(alpha, M, Nt, **kw):
 
 @pytest.mark.parametrize("alpha,M,Nt", [(1.5, 1, 2), (1.3, 2, 4), (1.7, 7, 3), (1.5, 63, 16),
                                         (1.8, 100, 7), (1.2, 1000, 8), (1.9, 255, 64),
-                                        (1.4, 300, 6), (1.6, 2000, 4), (1.3, 4096, 4)])
+                                        (1.4, 300, 6), (1.6, 2000, 4), (1.3, 4096, 4),
+                                        # orders whose pair count crosses a thread-slot
+                                        # boundary of the setup (256 pairs per slot)
+                                        (1.5, 515, 6), (1.7, 1026, 5), (1.2, 1539, 4)])
 def test_generators_and_shifted_solves(alpha, M, Nt):
     from paper_2003_07020_amd import capi
     banner(f"toeplitz small alpha={alpha} M={M} Nt={Nt}")

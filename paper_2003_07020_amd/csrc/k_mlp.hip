@@ -66,8 +66,10 @@ __global__ void __launch_bounds__(256) k_mlp_hidden(const float* __restrict__ fe
 }
 
 // ---- output layer: g[b][o] = sum_h h2[b][h] W3t[o][h] + b3[o] --------------------------------
-// One wave per 16 output columns and all batch rows (B <= 64, padded to 16-row blocks).
-template <int RB>
+// One wave per 16 output columns and all batch rows (B <= 64, padded to 16-row blocks).  VEC:
+// h2's BF16 copy and W3t's are 8-byte aligned, and a lane's four consecutive values of a k step
+// come as one 8-byte load (one access per lane instead of four).
+template <int RB, bool VEC>
 __global__ void __launch_bounds__(256) k_mlp_out(const unsigned short* __restrict__ h2b,
                                                  const unsigned short* __restrict__ W3b,
                                                  const float* __restrict__ b3, int B, int H2,
@@ -83,14 +85,25 @@ __global__ void __launch_bounds__(256) k_mlp_out(const unsigned short* __restric
   for (int k0 = 0; k0 < H2; k0 += 16) {
     const int kk = k0 + 4 * lq;
     ms4_t bv;
+    if constexpr (VEC) {
+      bv = *reinterpret_cast<const ms4_t*>(wrow + kk);
+    } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bv[j] = (short)wrow[kk + j];
+      for (int j = 0; j < 4; ++j) bv[j] = (short)wrow[kk + j];
+    }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int bb = r * 16 + l16;
-      ms4_t av;
+      ms4_t av = (ms4_t){0, 0, 0, 0};
+      if (bb < B) {
+        const unsigned short* hrow = h2b + (size_t)bb * H2 + kk;
+        if constexpr (VEC) {
+          av = *reinterpret_cast<const ms4_t*>(hrow);
+        } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) av[j] = bb < B ? (short)h2b[(size_t)bb * H2 + kk + j] : (short)0;
+          for (int j = 0; j < 4; ++j) av[j] = (short)hrow[j];
+        }
+      }
       acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[r], 0, 0, 0);
     }
   }
@@ -140,8 +153,10 @@ __global__ void __launch_bounds__(256) k_mlp_loss_final(const double* __restrict
 }
 
 // ---- dh2[b][h] = sum_o dg[b][o] W3t[o][h], split over chunks of KCH output columns -----------------
+// VEC: dg's BF16 copy is 8-byte aligned and a lane's four consecutive dg values of a k step come
+// as one 8-byte load.
 constexpr int KCH = 1024;
-template <int RB>
+template <int RB, bool VEC>
 __global__ void __launch_bounds__(256) k_mlp_dh2(const unsigned short* __restrict__ dgb,
                                                  const unsigned short* __restrict__ W3b, int B,
                                                  int H2, int NOUT, float* __restrict__ part) {
@@ -162,9 +177,16 @@ __global__ void __launch_bounds__(256) k_mlp_dh2(const unsigned short* __restric
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int bb = r * 16 + l16;
-        ms4_t av;
+        ms4_t av = (ms4_t){0, 0, 0, 0};
+        if (bb < B) {
+          const unsigned short* drow = dgb + (size_t)bb * NOUT + kk;
+          if constexpr (VEC) {
+            av = *reinterpret_cast<const ms4_t*>(drow);
+          } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) av[j] = bb < B ? (short)dgb[(size_t)bb * NOUT + kk + j] : (short)0;
+            for (int j = 0; j < 4; ++j) av[j] = (short)drow[j];
+          }
+        }
         acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[r], 0, 0, 0);
       }
     }
@@ -199,11 +221,12 @@ __device__ __forceinline__ void adam_apply(float& w, float& m, float& v, float g
 }
 
 // dW3t[o][h] = sum_b dg[b][o] h2[b][h] (FP32), db3[o] = sum_b dg[b][o]; Adam update of W3t and
-// its BF16 copy (mode 0) or plain gradient output (mode 1).  A thread owns four consecutive
-// weights of one output o (H2 % 16 == 0, so they share o): one dg load feeds four sums, the
-// h2 values come as one 16-byte load, and the batch loop is unrolled so that several rows'
-// loads are in flight; every sum still runs over b in order.  VEC: h2, the parameter arrays
-// (and the gradient output) are 16-byte aligned and are moved four values per access;
+// its BF16 copy (mode 0) or plain gradient output (mode 1).  A thread owns a 4 x 4 block of
+// weights: four consecutive outputs o (NOUT % 16 == 0) by four consecutive h (H2 % 16 == 0), so
+// each row's 16-byte h2 load feeds sixteen sums and each dg value four, and consecutive threads
+// take consecutive h (row accesses stay contiguous); the batch loop is unrolled so that several
+// rows' loads are in flight, and every sum still runs over b in order.  VEC: h2, the parameter
+// arrays (and the gradient output) are 16-byte aligned and are moved four values per access;
 // otherwise one value per access.
 template <bool VEC>
 __global__ void __launch_bounds__(256) k_mlp_w3(const float* __restrict__ dg,
@@ -214,63 +237,80 @@ __global__ void __launch_bounds__(256) k_mlp_w3(const float* __restrict__ dg,
                                                 float* __restrict__ b3, float* __restrict__ mb,
                                                 float* __restrict__ vb, AdamCfg a, int mode,
                                                 float* __restrict__ gW, float* __restrict__ gb) {
-  const size_t quads = (size_t)NOUT * H2 / 4;
-  const size_t qd = blockIdx.x * (size_t)256 + threadIdx.x;
-  if (qd >= quads) return;
-  const size_t e = 4 * qd;
-  const int o = (int)(e / H2), h = (int)(e % H2);
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-#pragma unroll 8
+  const int qr = H2 / 4;
+  const size_t units = (size_t)(NOUT / 4) * qr;
+  const size_t u = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (u >= units) return;
+  const int h = 4 * (int)(u % qr);
+  const int o0 = 4 * (int)(u / qr);
+  float sm[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sm[i][c] = 0.f;
+#pragma unroll 4
   for (int b = 0; b < B; ++b) {
-    const float d = dg[(size_t)b * NOUT + o];
     const float* hb = h2 + (size_t)b * H2 + h;
     float4 x;
     if constexpr (VEC) x = *reinterpret_cast<const float4*>(hb);
     else x = make_float4(hb[0], hb[1], hb[2], hb[3]);
-    s0 = fmaf(d, x.x, s0);
-    s1 = fmaf(d, x.y, s1);
-    s2 = fmaf(d, x.z, s2);
-    s3 = fmaf(d, x.w, s3);
-  }
-  if (mode == 1) {
-    if constexpr (VEC) {
-      *reinterpret_cast<float4*>(gW + e) = make_float4(s0, s1, s2, s3);
-    } else {
-      gW[e] = s0; gW[e + 1] = s1; gW[e + 2] = s2; gW[e + 3] = s3;
-    }
-  } else if constexpr (VEC) {
-    float4 w = *reinterpret_cast<const float4*>(W3t + e);
-    float4 m = *reinterpret_cast<const float4*>(mW + e);
-    float4 v = *reinterpret_cast<const float4*>(vW + e);
-    adam_apply(w.x, m.x, v.x, s0, a);
-    adam_apply(w.y, m.y, v.y, s1, a);
-    adam_apply(w.z, m.z, v.z, s2, a);
-    adam_apply(w.w, m.w, v.w, s3, a);
-    *reinterpret_cast<float4*>(W3t + e) = w;
-    *reinterpret_cast<float4*>(mW + e) = m;
-    *reinterpret_cast<float4*>(vW + e) = v;
-    const unsigned int lo = f2bf(w.x) | ((unsigned int)f2bf(w.y) << 16);
-    const unsigned int hi = f2bf(w.z) | ((unsigned int)f2bf(w.w) << 16);
-    *reinterpret_cast<uint2*>(W3b + e) = make_uint2(lo, hi);
-  } else {
-    const float sg[4] = {s0, s1, s2, s3};
+    const float* db = dg + (size_t)b * NOUT + o0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      float w = W3t[e + u], m = mW[e + u], v = vW[e + u];
-      adam_apply(w, m, v, sg[u], a);
-      W3t[e + u] = w; mW[e + u] = m; vW[e + u] = v;
-      W3b[e + u] = f2bf(w);
+    for (int i = 0; i < 4; ++i) {
+      const float d = db[i];
+      sm[i][0] = fmaf(d, x.x, sm[i][0]);
+      sm[i][1] = fmaf(d, x.y, sm[i][1]);
+      sm[i][2] = fmaf(d, x.z, sm[i][2]);
+      sm[i][3] = fmaf(d, x.w, sm[i][3]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const size_t e = (size_t)(o0 + i) * H2 + h;
+    if (mode == 1) {
+      if constexpr (VEC) {
+        *reinterpret_cast<float4*>(gW + e) = make_float4(sm[i][0], sm[i][1], sm[i][2], sm[i][3]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gW[e + c] = sm[i][c];
+      }
+    } else if constexpr (VEC) {
+      float4 w = *reinterpret_cast<const float4*>(W3t + e);
+      float4 m = *reinterpret_cast<const float4*>(mW + e);
+      float4 v = *reinterpret_cast<const float4*>(vW + e);
+      adam_apply(w.x, m.x, v.x, sm[i][0], a);
+      adam_apply(w.y, m.y, v.y, sm[i][1], a);
+      adam_apply(w.z, m.z, v.z, sm[i][2], a);
+      adam_apply(w.w, m.w, v.w, sm[i][3], a);
+      *reinterpret_cast<float4*>(W3t + e) = w;
+      *reinterpret_cast<float4*>(mW + e) = m;
+      *reinterpret_cast<float4*>(vW + e) = v;
+      const unsigned int lo = f2bf(w.x) | ((unsigned int)f2bf(w.y) << 16);
+      const unsigned int hi = f2bf(w.z) | ((unsigned int)f2bf(w.w) << 16);
+      *reinterpret_cast<uint2*>(W3b + e) = make_uint2(lo, hi);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float w = W3t[e + c], m = mW[e + c], v = vW[e + c];
+        adam_apply(w, m, v, sm[i][c], a);
+        W3t[e + c] = w; mW[e + c] = m; vW[e + c] = v;
+        W3b[e + c] = f2bf(w);
+      }
     }
   }
   if (h == 0) {
-    float sb = 0.f;
-    for (int b = 0; b < B; ++b) sb += dg[(size_t)b * NOUT + o];
-    if (mode == 1) {
-      gb[o] = sb;
-    } else {
-      float w = b3[o], m = mb[o], v = vb[o];
-      adam_apply(w, m, v, sb, a);
-      b3[o] = w; mb[o] = m; vb[o] = v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int o = o0 + i;
+      float sb = 0.f;
+      for (int b = 0; b < B; ++b) sb += dg[(size_t)b * NOUT + o];
+      if (mode == 1) {
+        gb[o] = sb;
+      } else {
+        float w = b3[o], m = mb[o], v = vb[o];
+        adam_apply(w, m, v, sb, a);
+        b3[o] = w; mb[o] = m; vb[o] = v;
+      }
     }
   }
 }
@@ -452,12 +492,16 @@ static int mlp_forward_impl(const rfde_mlp* m, const float* feats, int B, float*
   RFDE_HIP(hipGetLastError());
   const int blocks = (m->NOUT / 16 + 3) / 4;
   const int RB = (B + 15) / 16;
+  const bool vec = ((uintptr_t)m->W3t_bf16 & 7) == 0 && ((uintptr_t)w.h2b & 7) == 0;
+#define RFDE_MLP_OUT(R, V) \
+  k_mlp_out<R, V><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g)
   switch (RB) {
-    case 1: k_mlp_out<1><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g); break;
-    case 2: k_mlp_out<2><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g); break;
-    case 3: k_mlp_out<3><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g); break;
-    default: k_mlp_out<4><<<blocks, 256, 0, st>>>(w.h2b, m->W3t_bf16, m->b3, B, m->H2, m->NOUT, g); break;
+    case 1: if (vec) RFDE_MLP_OUT(1, true); else RFDE_MLP_OUT(1, false); break;
+    case 2: if (vec) RFDE_MLP_OUT(2, true); else RFDE_MLP_OUT(2, false); break;
+    case 3: if (vec) RFDE_MLP_OUT(3, true); else RFDE_MLP_OUT(3, false); break;
+    default: if (vec) RFDE_MLP_OUT(4, true); else RFDE_MLP_OUT(4, false); break;
   }
+#undef RFDE_MLP_OUT
   RFDE_HIP(hipGetLastError());
   return RFDE_OK;
 }
@@ -526,12 +570,16 @@ static int mlp_backward(const rfde_mlp* m, const float* feats, const float* y, i
   RFDE_HIP(hipGetLastError());
   const int nchunk = (m->NOUT + KCH - 1) / KCH;
   const int RB = (B + 15) / 16;
+  const bool dvec = ((uintptr_t)w.dgb & 7) == 0;
+#define RFDE_MLP_DH2(R, V) \
+  k_mlp_dh2<R, V><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part)
   switch (RB) {
-    case 1: k_mlp_dh2<1><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part); break;
-    case 2: k_mlp_dh2<2><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part); break;
-    case 3: k_mlp_dh2<3><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part); break;
-    default: k_mlp_dh2<4><<<nchunk, 256, 0, st>>>(w.dgb, m->W3t_bf16, B, m->H2, m->NOUT, w.dh2part); break;
+    case 1: if (dvec) RFDE_MLP_DH2(1, true); else RFDE_MLP_DH2(1, false); break;
+    case 2: if (dvec) RFDE_MLP_DH2(2, true); else RFDE_MLP_DH2(2, false); break;
+    case 3: if (dvec) RFDE_MLP_DH2(3, true); else RFDE_MLP_DH2(3, false); break;
+    default: if (dvec) RFDE_MLP_DH2(4, true); else RFDE_MLP_DH2(4, false); break;
   }
+#undef RFDE_MLP_DH2
   RFDE_HIP(hipGetLastError());
   const int BH = B * m->H2;
   k_mlp_dh2_reduce<<<(BH + 255) / 256, 256, 0, st>>>(w.dh2part, nchunk, BH, w.dh2);
@@ -560,7 +608,7 @@ static int mlp_backward(const rfde_mlp* m, const float* feats, const float* y, i
   k_mlp_small_update<<<(nsmall + 255) / 256, 256, 0, st>>>(w.phat, w.h1, w.da2, w.da1, B,
                                                             m->Pin, m->H1, m->H2, P, a, mode);
   RFDE_HIP(hipGetLastError());
-  const size_t quads = (size_t)m->NOUT * m->H2 / 4;
+  const size_t quads = (size_t)(m->NOUT / 4) * (m->H2 / 4);  // 4 x 4 weight blocks
   float* gW3 = grads ? grads + oW3 : nullptr;
   auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
   const bool vec = al16(w.h2) &&

@@ -10,7 +10,8 @@ solver's true FP64 residual decides convergence, and a zero guess is the fallbac
 guess's residual is not smaller than ||F||.
 
 Training data are produced by the method itself: for each drawn (alpha, kappa) one plan is
-created and the 16 unit components are solved (16 FP64 solves per draw), then projected on the
+created (by default with the factor-free exact step (b)) and the 16 unit components are solved
+(16 FP64 solves per draw), then projected on the
 first Ks sine modes (rfde_project_sine).  Targets are scaled by 1/mode^2, the standard deviation
 of the synthetic coefficients, so the loss weighs each component by its share in a typical
 solution.
@@ -172,9 +173,11 @@ class LearnedGuess:
     def features(self, alpha, kappa):
         return [alpha, math.log(kappa), math.log(self.tau / self.h ** alpha)]
 
-    def generate(self, draws, tol=1e-8, log=None):
-        """Targets for a list of (alpha, kappa): 16 FP64 solves per draw.  Returns (feats, Y)
-        device tensors, Y scaled per component (B x NOUT, float32), and the solve count."""
+    def generate(self, draws, tol=1e-8, spatial="toeplitz", log=None):
+        """Targets for a list of (alpha, kappa): 16 FP64 solves per draw, by default with the
+        factor-free exact step (b) (the same preconditioner as the LDL^T form, without the
+        factorisation: its setup is cheap enough to amortise over 16 solves).  Returns (feats,
+        Y) device tensors, Y scaled per component (B x NOUT, float32), and the solve count."""
         n = len(draws)
         Y = torch.empty((n, self.NOUT), dtype=torch.float32, device="cuda")
         feats = torch.tensor([self.features(a, k) for a, k in draws], dtype=torch.float32,
@@ -184,7 +187,8 @@ class LearnedGuess:
         solves = 0
         t0 = time.perf_counter()
         for d, (alpha, kappa) in enumerate(draws):
-            with Plan.create_1d(alpha, kappa, 0.0, 1.0, self.M, self.Nt, self.T, tol=tol) as p:
+            with Plan.create_1d(alpha, kappa, 0.0, 1.0, self.M, self.Nt, self.T, tol=tol,
+                                spatial=spatial) as p:
                 for j, (u0, f) in enumerate(self.units):
                     p.solve(u0, f, out=U)
                     solves += 1

@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels-only", action="store_true")
     ap.add_argument("--precond-bits", type=int, default=64, choices=[64, 32])
-    ap.add_argument("--learned-train", type=int, default=625)
+    ap.add_argument("--learned-train", type=int, default=1250)
     ap.add_argument("--learned-epochs", type=int, default=2000)
     ap.add_argument("--learned-heldout", type=int, default=1000)
     ap.add_argument("--learned-ks", type=int, default=64)
